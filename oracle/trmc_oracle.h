@@ -1,0 +1,47 @@
+/*
+ * trmc_oracle.h -- interface of the FP64 CPU oracle (test infrastructure only).
+ * Private to oracle/: the GPU library neither includes nor links this file.
+ */
+#ifndef TRMC_ORACLE_H
+#define TRMC_ORACLE_H
+#include <stdint.h>
+
+enum { ORC_HOMOG = 1, ORC_SLAB = 2 };
+enum { ORC_NATURAL = 0, ORC_FIXED = 1, ORC_ADAPTIVE = 2 };
+
+typedef struct {
+    uint32_t seed, uid;
+    uint32_t geometry;   /* ORC_HOMOG: one cell; ORC_SLAB: [0, length] split in n_cells */
+    uint32_t n_cells;
+    double length;       /* slab length, or the volume of a homogeneous instance */
+    double dt;
+    double weight;       /* mass carried by one particle: rho_c = n_c * weight / V_c */
+    double eps;          /* Knudsen number when eps_cells is NULL */
+    const double* eps_cells;
+    double alpha;        /* VHS exponent: 0 Maxwell molecules, 1 hard spheres */
+    uint32_t trunc, m_init, m_cap;
+    double delta1, delta2;
+} orc_desc;
+
+typedef struct {
+    uint32_t n, N0, m_eff, m_used, attempts, R0, n_th, borrowed, folds, m_state_after;
+    uint64_t collisions, dummies, violations, work_collisions;
+    double q, g, E1;
+} orc_cell_record;
+
+void orc_philox(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]);
+double orc_exp_neg(double x);
+double orc_grid_up(double g);
+uint32_t orc_perm(uint32_t i, uint32_t n, const uint32_t k[4]);
+uint32_t orc_transport(double* x, double* vx, double dt, double L, uint32_t n_cells);
+int orc_run(const orc_desc* d, uint64_t n, double* x, double* vx, double* vy, double* vz,
+            uint32_t* m_state, uint32_t step0, uint32_t n_steps, orc_cell_record* rec,
+            uint32_t* cell_counts);
+void orc_moments(uint64_t n, const double* vx, const double* vy, const double* vz, double rho_factor,
+                 double out[9]);
+int orc_split(uint32_t seed, uint32_t uid, uint32_t cell, uint32_t step, uint32_t n, double q, uint32_t m,
+              uint64_t* N_out, uint32_t* m_eff_out);
+int orc_collide(const double a[3], const double b[3], double xi1, double xi2, double xacc, double alpha,
+                double g, double oa[3], double ob[3]);
+
+#endif

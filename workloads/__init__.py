@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module draws initial particle states and instance parameters only; it holds
+none of the collision method's arithmetic.  All generators use numpy's PCG64 with
+an explicit seed so that both sides of a parity test start from identical arrays.
+
+Initial data (the paper's own tests use sums of Maxwellians and a Rankine-Hugoniot
+shock; its data files are not available, so these synthetic recipes stand in):
+  - BKW: the Bobylev / Krook-Wu similarity solution for Maxwell molecules at
+    shape parameter K (mass 1, zero mean, temperature 1);
+  - bi-Maxwellian: two unit-temperature Gaussians with means +-(1, 0, 0);
+  - Sod-type slab: left half density 1 / temperature 1, right half density 0.125 /
+    temperature 0.8, positions uniform inside each cell.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def rng(seed: int, stream: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([int(seed), int(stream)]))
+
+
+def bkw(n: int, K: float = 0.6, seed: int = 0, stream: int = 0):
+    """Velocities from the BKW density with shape K (3/5 <= K <= 1).
+
+    f = G_K(v) [ (5K-3)/(2K) + (1-K)|v|^2/(2K^2) ] with G_K the N(0, K I) density:
+    with probability (5K-3)/(2K) a N(0, K I) sample, otherwise an isotropic sample
+    with |v|^2 / K distributed chi-square with 5 degrees of freedom.
+    """
+    g = rng(seed, stream)
+    p_gauss = (5.0 * K - 3.0) / (2.0 * K)
+    gauss = g.random(n) < p_gauss
+    v = g.standard_normal((n, 3)) * math.sqrt(K)
+    m = int((~gauss).sum())
+    if m:
+        r = np.sqrt(K * g.chisquare(5, m))
+        d = g.standard_normal((m, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        v[~gauss] = d * r[:, None]
+    return v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy()
+
+
+def bkw_m4(t_over_eps: float, K0: float = 0.6) -> float:
+    """Fourth moment of the BKW solution: 15 K (2 - K), 1 - K(t) = (1 - K0) e^{-t/6}
+    for the normalised Maxwell kernel (total collision rate 1 at density 1)."""
+    one_minus_K = (1.0 - K0) * math.exp(-t_over_eps / 6.0)
+    return 15.0 - 15.0 * one_minus_K * one_minus_K
+
+
+def bimaxwellian(n: int, seed: int = 0, stream: int = 0):
+    """Two unit-temperature Gaussians with means +(1,0,0) (even ids) and -(1,0,0) (odd ids)."""
+    g = rng(seed, stream)
+    v = g.standard_normal((n, 3))
+    sign = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    v[:, 0] += sign
+    return v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy()
+
+
+def maxwellian(n: int, u=(0.0, 0.0, 0.0), T: float = 1.0, seed: int = 0, stream: int = 0):
+    g = rng(seed, stream)
+    v = g.standard_normal((n, 3)) * math.sqrt(T) + np.asarray(u)[None, :]
+    return v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy()
+
+
+def sod(n_cells: int, ppc_left: int, ppc_right: int, length: float = 1.0, T_left: float = 1.0,
+        T_right: float = 0.8, seed: int = 0, stream: int = 0):
+    """Sod-type slab: particles per cell ppc_left on the left half, ppc_right on the right.
+
+    Returns x, vx, vy, vz and the particle weight w = (L / n_cells) / ppc_left, so that
+    the left density is 1 and the right density is ppc_right / ppc_left.
+    Particles are generated cell by cell, positions uniform in the cell.
+    """
+    g = rng(seed, stream)
+    dx = length / n_cells
+    xs, vs = [], []
+    for c in range(n_cells):
+        left = c < n_cells // 2
+        m = ppc_left if left else ppc_right
+        T = T_left if left else T_right
+        xs.append(c * dx + g.random(m) * dx)
+        vs.append(g.standard_normal((m, 3)) * math.sqrt(T))
+    x = np.concatenate(xs)
+    v = np.concatenate(vs)
+    w = dx / ppc_left
+    return x, v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy(), w
+
+
+def sod_dt(length: float, n_cells: int, cfl: float = 0.5, v_ref: float = 3.0) -> float:
+    """dt = CFL * dx / v_ref with v_ref = max over the two states of |u| + 3 sqrt(T) = 3."""
+    return cfl * (length / n_cells) / v_ref
+
+
+def transition_eps(n_cells: int, lo: float = 1e-4, hi: float = 1.0):
+    """eps(x) log-linear from lo to hi across the cells (cell centres)."""
+    c = (np.arange(n_cells) + 0.5) / n_cells
+    return lo * (hi / lo) ** c
+
+
+def batched_homogeneous(n_inst: int, seed: int = 0, n_min: int = 256, n_max: int = 65536,
+                        eps_min: float = 1e-4, eps_max: float = 10.0):
+    """Parameters of a batch of independent homogeneous instances.
+
+    N log-uniform in [n_min, n_max], eps log-uniform in [eps_min, eps_max], Maxwell
+    molecules (alpha 0) and hard spheres (alpha 1) alternating, BKW initial data for
+    instances with floor(i/2) even and bi-Maxwellian for the others.
+    """
+    g = rng(seed, 7)
+    u1 = g.random(n_inst)
+    u2 = g.random(n_inst)
+    N = np.rint(n_min * (n_max / n_min) ** u1).astype(np.int64)
+    eps = eps_min * (eps_max / eps_min) ** u2
+    alpha = (np.arange(n_inst) % 2).astype(np.float64)
+    init = np.where((np.arange(n_inst) // 2) % 2 == 0, 0, 1)  # 0 BKW, 1 bi-Maxwellian
+    return N, eps, alpha, init
+
+
+def batched_velocities(N, init, seed: int = 0, K0: float = 0.6):
+    """Concatenated initial velocities for the batch (instance i uses stream 1000 + i)."""
+    vx, vy, vz = [], [], []
+    for i, (n, kind) in enumerate(zip(N, init)):
+        a = bkw(int(n), K0, seed, 1000 + i) if kind == 0 else bimaxwellian(int(n), seed, 1000 + i)
+        vx.append(a[0]); vy.append(a[1]); vz.append(a[2])
+    return np.concatenate(vx), np.concatenate(vy), np.concatenate(vz)
