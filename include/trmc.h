@@ -1,0 +1,178 @@
+/*
+ * trmc.h -- C ABI of the MI355X (gfx950) TRMC-R library.
+ *
+ * One time step is the first-order splitting of Sec. 3.1 of Trazzi, Pareschi and
+ * Wennberg: free flight (1-D slab only), a stable counting sort of the particles
+ * by cell, then the space-homogeneous collision step of every cell by recursive
+ * time-relaxed Monte Carlo (Alg. 4.2 split into collision sets, Alg. 4.3 / 4.4
+ * recursive collision trees with dummy collisions, Maxwellian remainder) with
+ * optional adaptive depth (Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: 0 on success, a negative errno-style code otherwise
+ *     (TRMC_EINVAL, TRMC_ENOMEM, TRMC_ENOSPC, TRMC_EIO, TRMC_EOVERFLOW);
+ *     trmc_strerror() gives the text.  No exception crosses the ABI.
+ *   - Arguments are validated before anything is enqueued; a failing call leaves
+ *     the context unchanged.  Errors of asynchronous GPU work surface at the next
+ *     synchronising call (trmc_sync, trmc_moments, trmc_read).
+ *   - Device memory is never allocated or freed by the library: particle arrays
+ *     and workspaces are owned by the caller and must outlive the context.
+ *   - Work is enqueued on the HIP stream given at creation; calls on one context
+ *     must come from one host thread at a time.
+ *   - Results depend only on (descriptor, initial particles, number of steps):
+ *     not on the slot an instance occupies, on the other instances in the batch,
+ *     or on launch shapes.
+ */
+#ifndef TRMC_H
+#define TRMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRMC_ABI_VERSION 1
+
+#define TRMC_EINVAL (-22)
+#define TRMC_ENOMEM (-12)
+#define TRMC_ENOSPC (-28)
+#define TRMC_EIO (-5)
+#define TRMC_EOVERFLOW (-75)
+
+/* geometry */
+#define TRMC_HOMOG 1  /* one space-homogeneous cell (eq. HOM-r), no transport */
+#define TRMC_SLAB1D 2 /* slab [0, length], n_cells equal cells, specular walls */
+/* precision */
+#define TRMC_FP64 1        /* velocities, positions and all arithmetic in double */
+#define TRMC_FP32_MIXED 2  /* float velocities/positions and collision arithmetic;
+                              double per-cell sums and conservation rescale */
+/* truncation of the collision trees */
+#define TRMC_NATURAL 0  /* depth limited only by m_cap */
+#define TRMC_FIXED 1    /* depth m_init every step */
+#define TRMC_ADAPTIVE 2 /* depth adapted per cell from m_init (Sec. 4.3) */
+
+typedef struct trmc_ctx trmc_ctx;
+
+/* One instance: a homogeneous solve or a 1-D slab.  Host memory, read at admission. */
+typedef struct trmc_desc {
+    uint32_t struct_size;   /* sizeof(trmc_desc) (ABI guard) */
+    uint32_t seed;          /* Philox key word 0 */
+    uint32_t uid;           /* Philox key word 1: a request-stable id, never a slot number */
+    uint32_t geometry;      /* TRMC_HOMOG or TRMC_SLAB1D */
+    uint64_t n_particles;   /* 2 .. 2^31 */
+    uint32_t n_cells;       /* 1 for TRMC_HOMOG; 1 .. 12288 for TRMC_SLAB1D */
+    uint32_t precision;     /* TRMC_FP64 or TRMC_FP32_MIXED */
+    double length;          /* slab length L, or the volume of a homogeneous instance */
+    double dt;              /* time step */
+    double particle_weight; /* mass of one particle: rho_c = n_c * weight / (cell volume) */
+    double eps;             /* Knudsen number, used when eps_cells is NULL */
+    const double* eps_cells;/* host [n_cells] Knudsen number per cell, or NULL */
+    double alpha;           /* VHS exponent of B = K |q|^alpha, K = 1/(4 pi): 0 Maxwell molecules, 1 hard spheres */
+    uint32_t trunc;         /* TRMC_NATURAL / TRMC_FIXED / TRMC_ADAPTIVE */
+    uint32_t m_init;        /* initial (ADAPTIVE) or fixed (FIXED) depth, >= 1 */
+    uint32_t m_cap;         /* maximum depth, 1 .. 2048 */
+    uint32_t step0;         /* index of the first step (restart from a saved state) */
+    double delta1, delta2;  /* adaptive thresholds, 0 < delta1 < delta2 (Sec. 4.3) */
+    const uint32_t* m_state0; /* host [n_cells] saved adaptive depths, or NULL (use m_init) */
+} trmc_desc;
+
+/* Caller-owned device arrays of one instance, SoA, n_particles elements each, of
+ * double (TRMC_FP64) or float (TRMC_FP32_MIXED).  x is ignored (may be NULL) for
+ * TRMC_HOMOG.  A slab's particles may be in any order and any cell at admission. */
+typedef struct trmc_particles {
+    void* x;
+    void* vx;
+    void* vy;
+    void* vz;
+} trmc_particles;
+
+/* Per-cell moments of the current state (Sec. 2 and 5.1: rho, u, T, P_ii, M4 per
+ * unit mass) and counters of the last step (the paper's cost unit of Sec. 5:
+ * collisions, and Maxwellian samples). */
+typedef struct trmc_cell_moments {
+    uint32_t n;            /* particles in the cell */
+    uint32_t m_state;      /* adaptive depth for the next step */
+    double rho, ux, uy, uz, T, Pxx, Pyy, Pzz, M4;
+    uint64_t collisions;   /* collisions of the accepted tree (real + dummy) */
+    uint64_t dummies;      /* rejected (dummy) collisions, VHS only */
+    uint64_t violations;   /* pairs whose |q|^alpha exceeded the majorant */
+    uint64_t work_collisions; /* collisions over all adaptive attempts */
+    uint32_t thermalized;  /* particles replaced by Maxwellian samples */
+    uint32_t borrowed;     /* leaves taken from the unchanged block */
+    uint32_t m_eff;        /* depth of the accepted tree */
+    uint32_t m_used;       /* truncation depth of the accepted attempt */
+    uint32_t attempts;     /* adaptive attempts (1 = accepted at once) */
+    uint32_t N0;           /* particles kept unchanged by the split */
+    uint32_t R0;           /* leaves (initial-density samples) used by the trees */
+    uint32_t status;       /* 0, or TRMC_CELL_* flags */
+    double q;              /* exp(-mu dt / eps) = 1 - tau */
+    double g;              /* majorant (2 dv)^alpha on the 20-bit grid */
+} trmc_cell_moments;
+
+#define TRMC_CELL_OVERFLOW 1u /* scratch too small for this cell's trees: cell left unchanged */
+
+/* Bytes of device workspace needed by these instances (pure, host only): the
+ * slab double buffer, sort histograms, per-cell state and collision scratch.
+ * Fails with TRMC_EINVAL on an invalid descriptor. */
+int trmc_workspace_size(const trmc_desc* descs, uint32_t n_inst, size_t* bytes);
+
+/* Bytes of device workspace of the context itself: instance and work tables for
+ * up to max_instances instances and max_cells cells (pure, host only). */
+int trmc_ctx_workspace_size(uint32_t max_instances, uint32_t max_cells, size_t* bytes);
+
+/* Create a context holding the given instances, all stepped together by trmc_step.
+ * descs/bufs: host arrays of n_inst entries (n_inst may be 0); workspace:
+ * caller-owned device memory, 256-byte aligned, of at least
+ * trmc_ctx_workspace_size(max_instances, max_cells) + trmc_workspace_size(descs,
+ * n_inst) bytes; hip_stream: a hipStream_t (NULL = default stream).  Capacity
+ * for later admissions: max_instances (>= n_inst) instances and max_cells cells
+ * in total. */
+int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trmc_particles* bufs,
+              void* workspace, size_t workspace_bytes, uint32_t max_instances, uint32_t max_cells,
+              void* hip_stream);
+
+/* Advance every active instance by n_steps steps (transport, sort, collisions),
+ * asynchronously on the context's stream. */
+int trmc_step(trmc_ctx* ctx, uint32_t n_steps);
+
+/* Moments and counters of instance `slot`, one entry per cell (cap >= n_cells).
+ * Synchronises the stream. */
+int trmc_moments(trmc_ctx* ctx, uint32_t slot, trmc_cell_moments* host_out, uint32_t cap);
+
+/* Current device arrays of instance `slot` (a slab alternates between the
+ * caller's arrays and a workspace copy; the pointers change after every step). */
+int trmc_state(trmc_ctx* ctx, uint32_t slot, trmc_particles* out);
+
+/* Copy the current particles of `slot` to host arrays (any may be NULL), in cell
+ * order for a slab; m_state (host [n_cells], may be NULL) receives the adaptive
+ * depths; *step receives the index of the next step.  Synchronises the stream. */
+int trmc_read(trmc_ctx* ctx, uint32_t slot, void* x, void* vx, void* vy, void* vz, uint32_t* m_state,
+              uint32_t* step);
+
+/* Serving: add one instance while others run.  workspace: its own caller-owned
+ * device memory of trmc_workspace_size(desc, 1) bytes.  On success *slot receives
+ * the slot number.  TRMC_ENOSPC when the slot table or the cell capacity is full. */
+int trmc_admit(trmc_ctx* ctx, const trmc_desc* desc, const trmc_particles* buf, void* workspace,
+               size_t workspace_bytes, uint32_t* slot);
+
+/* Remove instance `slot` from the active set (its memory is the caller's again
+ * once the stream has passed this point). */
+int trmc_retire(trmc_ctx* ctx, uint32_t slot);
+
+/* Wait for the stream and report any asynchronous error. */
+int trmc_sync(trmc_ctx* ctx);
+
+/* Destroy the context (never frees caller memory). */
+int trmc_destroy(trmc_ctx* ctx);
+
+const char* trmc_strerror(int status);
+
+/* ABI version compiled into the library. */
+int trmc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -220,7 +220,8 @@ class Instance:
         vol = self.length / nc if self.geometry == SLAB else self.length
         out = np.zeros((nc, 9))
         if self.geometry == SLAB:
-            starts = np.concatenate([[0], np.cumsum(self.counts)]) if hasattr(self, "counts") else None
+            starts = (np.concatenate([[0], np.cumsum(self.counts.astype(np.int64))]).astype(np.int64)
+                      if hasattr(self, "counts") else None)
             if starts is None:
                 raise RuntimeError("moments of a slab need at least one step (cells are sorted by it)")
         else:

@@ -601,11 +601,13 @@ uint32_t orc_transport(double* x, double* vx, double dt, double L, uint32_t n_ce
 {
     double xn = fma(*vx, dt, *x);
     double u = *vx;
-    while (xn < 0.0 || xn > L) {
+    for (int it = 0; (xn < 0.0 || xn > L) && it < 64; ++it) {
         if (xn < 0.0) xn = -xn;
         else xn = 2.0 * L - xn;
         u = -u;
     }
+    if (xn < 0.0) xn = 0.0; /* at most 64 wall crossings per step; only non-finite input gets here */
+    if (xn > L) xn = L;
     *x = xn;
     *vx = u;
     double inv_dx = (double)n_cells / L;

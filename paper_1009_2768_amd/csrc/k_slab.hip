@@ -1,0 +1,294 @@
+// k_slab.hip -- free flight in a slab with specular walls, stable counting sort
+// of the particles by cell (the transport half of the first-order splitting of
+// Sec. 3.1), per-cell moments, and the per-step advance of instance counters.
+//
+// Sort: the particles of an instance are cut into tiles of `tile` consecutive
+// particles.  k_hist counts the new cells of each tile (LDS histogram, written
+// densely as hist[tile][cell]); k_scan_tiles turns every column into exclusive
+// tile bases and the column totals into cell offsets; k_scatter walks each tile
+// in order, ranks equal cells inside a wave with ballots and across the waves of
+// a chunk with short per-wave lists, and writes every particle to
+// offset[cell] + base[tile][cell] + (earlier particles of that cell in the tile).
+// The result is the stable order: by cell, then by previous position.
+#include <hip/hip_runtime.h>
+
+#include "trmc_device.h"
+#include "trmc_internal.h"
+
+namespace trmc {
+
+template <typename T>
+__device__ __forceinline__ uint32_t slab_move(T& x, T& v, T dt, T L, double inv_dx, uint32_t nc);
+
+template <>
+__device__ __forceinline__ uint32_t slab_move<double>(double& x, double& v, double dt, double L, double inv_dx,
+                                                      uint32_t nc)
+{
+#pragma clang fp contract(off)
+    double xn = fma(v, dt, x);
+    double u = v;
+    for (int it = 0; (xn < 0.0 || xn > L) && it < 64; ++it) {
+        if (xn < 0.0) xn = -xn;
+        else xn = 2.0 * L - xn;
+        u = -u;
+    }
+    xn = xn < 0.0 ? 0.0 : (xn > L ? L : xn);  // only non-finite input gets here
+    x = xn;
+    v = u;
+    const double cf = floor(xn * inv_dx);
+    return cf < 0.0 ? 0u : (cf >= (double)nc ? nc - 1u : (uint32_t)cf);
+}
+
+template <>
+__device__ __forceinline__ uint32_t slab_move<float>(float& x, float& v, float dt, float L, double inv_dx,
+                                                     uint32_t nc)
+{
+#pragma clang fp contract(off)
+    float xn = fmaf(v, dt, x);
+    float u = v;
+    for (int it = 0; (xn < 0.0f || xn > L) && it < 64; ++it) {
+        if (xn < 0.0f) xn = -xn;
+        else xn = 2.0f * L - xn;
+        u = -u;
+    }
+    xn = xn < 0.0f ? 0.0f : (xn > L ? L : xn);  // only non-finite input gets here
+    x = xn;
+    v = u;
+    const double cf = floor((double)xn * inv_dx);
+    return cf < 0.0 ? 0u : (cf >= (double)nc ? nc - 1u : (uint32_t)cf);
+}
+
+// Tile size used by the sort of an instance with n_cells cells: at least 4 cells'
+// worth of counters per particle... i.e. the dense histogram costs <= 1 byte per particle.
+__host__ __device__ inline uint32_t sort_tile(uint32_t n_cells)
+{
+    uint32_t t = 4u * n_cells;
+    t = (t + 1023u) & ~1023u;
+    return t < kSortTile ? kSortTile : t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_hist(InstDev* __restrict__ I)
+{
+    extern __shared__ uint32_t hist[];
+    const uint32_t nc = I->n_cells;
+    const uint32_t tile = sort_tile(nc);
+    const uint64_t n = I->n;
+    const uint64_t t0 = (uint64_t)blockIdx.x * tile;
+    const uint64_t t1 = (t0 + tile < n) ? t0 + tile : n;
+    for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+    const uint32_t cur = I->cur;
+    const T* __restrict__ x = reinterpret_cast<const T*>(I->x[cur]);
+    const T* __restrict__ vx = reinterpret_cast<const T*>(I->vx[cur]);
+    const T dt = (T)I->dt, L = (T)I->length;
+    const double inv_dx = I->inv_dx;
+    for (uint64_t p = t0 + threadIdx.x; p < t1; p += blockDim.x) {
+        T xp = x[p], vp = vx[p];
+        const uint32_t c = slab_move<T>(xp, vp, dt, L, inv_dx, nc);
+        atomicAdd(&hist[c], 1u);
+    }
+    __syncthreads();
+    uint32_t* out = I->hist + (uint64_t)blockIdx.x * nc;
+    for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) out[c] = hist[c];
+}
+
+// Column scan over tiles: hist[t][c] <- sum_{t' < t} hist[t'][c]; totals to cell_off.
+__global__ __launch_bounds__(256) void k_scan_tiles(InstDev* __restrict__ I)
+{
+    const uint32_t nc = I->n_cells;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const uint32_t nt = I->n_tiles;
+    uint32_t acc = 0;
+    for (uint32_t t = 0; t < nt; ++t) {
+        uint32_t* h = I->hist + (uint64_t)t * nc + c;
+        const uint32_t v = *h;
+        *h = acc;
+        acc += v;
+    }
+    I->cell_off[c + 1] = acc;  // counts, scanned by k_scan_cells
+}
+
+// Exclusive scan of the cell counts (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_scan_cells(InstDev* __restrict__ I)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t nc = I->n_cells;
+    const uint32_t per = (nc + 1023u) / 1024u;
+    const uint32_t b = threadIdx.x * per;
+    const uint32_t e = (b + per < nc) ? b + per : nc;
+    uint32_t s = 0;
+    for (uint32_t c = b; c < e; ++c) s += I->cell_off[c + 1];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t o = 1; o < 1024u; o <<= 1) {
+        const uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    // cell_off[c + 1] holds the count of cell c; each thread turns its own range
+    // [b + 1, e] into offsets (read and written by the same thread only).
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (uint32_t c = b; c < e; ++c) {
+        run += I->cell_off[c + 1];
+        I->cell_off[c + 1] = run;
+    }
+    if (threadIdx.x == 0) I->cell_off[0] = 0u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scatter(InstDev* __restrict__ I)
+{
+    extern __shared__ uint32_t run[];              // [nc] next destination of each cell in this tile
+    __shared__ uint32_t wl_cell[16][64];           // per-wave distinct cells of the chunk
+    __shared__ uint32_t wl_cnt[16][64];
+    __shared__ uint32_t wl_pre[16][64];
+    __shared__ uint32_t wl_n[16];
+    const uint32_t nc = I->n_cells;
+    const uint32_t tile = sort_tile(nc);
+    const uint64_t n = I->n;
+    const uint64_t t0 = (uint64_t)blockIdx.x * tile;
+    const uint64_t t1 = (t0 + tile < n) ? t0 + tile : n;
+    const uint32_t* base = I->hist + (uint64_t)blockIdx.x * nc;
+    for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) run[c] = I->cell_off[c] + base[c];
+    __syncthreads();
+    const uint32_t cur = I->cur, nxt = cur ^ 1u;
+    const T* __restrict__ x = reinterpret_cast<const T*>(I->x[cur]);
+    const T* __restrict__ vx = reinterpret_cast<const T*>(I->vx[cur]);
+    const T* __restrict__ vy = reinterpret_cast<const T*>(I->vy[cur]);
+    const T* __restrict__ vz = reinterpret_cast<const T*>(I->vz[cur]);
+    T* __restrict__ ox = reinterpret_cast<T*>(I->x[nxt]);
+    T* __restrict__ ovx = reinterpret_cast<T*>(I->vx[nxt]);
+    T* __restrict__ ovy = reinterpret_cast<T*>(I->vy[nxt]);
+    T* __restrict__ ovz = reinterpret_cast<T*>(I->vz[nxt]);
+    const T dt = (T)I->dt, L = (T)I->length;
+    const double inv_dx = I->inv_dx;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64u - lane));
+    for (uint64_t cb = t0; cb < t1; cb += blockDim.x) {
+        const uint64_t p = cb + threadIdx.x;
+        const bool valid = p < t1;
+        T xp = T(0), vp = T(0), wy = T(0), wz = T(0);
+        uint32_t c = 0;
+        if (valid) {
+            xp = x[p];
+            vp = vx[p];
+            wy = vy[p];
+            wz = vz[p];
+            c = slab_move<T>(xp, vp, dt, L, inv_dx, nc);
+        }
+        // distinct cells of the wave, in lane order of first appearance
+        bool pend = valid;
+        uint32_t my_rank = 0, my_k = 0, k = 0;
+        for (;;) {
+            const unsigned long long m = __ballot(pend);
+            if (m == 0ull) break;
+            const uint32_t d = (uint32_t)__shfl((int)c, __ffsll((long long)m) - 1);
+            const bool hit = pend && c == d;
+            const unsigned long long e = __ballot(hit);
+            if (hit) {
+                my_rank = (uint32_t)__popcll(e & lt);
+                my_k = k;
+                pend = false;
+            }
+            if (lane == 0) {
+                wl_cell[wave][k] = d;
+                wl_cnt[wave][k] = (uint32_t)__popcll(e);
+            }
+            ++k;
+        }
+        if (lane == 0) wl_n[wave] = k;
+        __syncthreads();
+        // prefix over earlier waves of the same cell (leaders only)
+        if (valid && my_rank == 0) {
+            uint32_t pre = 0;
+            for (uint32_t w = 0; w < wave; ++w) {
+                const uint32_t kn = wl_n[w];
+                for (uint32_t kk = 0; kk < kn; ++kk) pre += (wl_cell[w][kk] == c) ? wl_cnt[w][kk] : 0u;
+            }
+            wl_pre[wave][my_k] = pre;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t dst = run[c] + wl_pre[wave][my_k] + my_rank;
+            ox[dst] = xp;
+            ovx[dst] = vp;
+            ovy[dst] = wy;
+            ovz[dst] = wz;
+        }
+        __syncthreads();
+        if (valid && my_rank == 0) atomicAdd(&run[c], wl_cnt[wave][my_k]);
+        __syncthreads();
+        (void)nw;
+    }
+}
+
+// Per-cell moments (FP64): rho, u, T, P_xx, P_yy, P_zz, M4 per unit mass.
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments(const CellRef* __restrict__ work, uint32_t n_work)
+{
+    __shared__ double red[4 * 8];
+    const uint32_t wi = blockIdx.x;
+    if (wi >= n_work) return;
+    InstDev* __restrict__ I = work[wi].inst;
+    const uint32_t cell = work[wi].cell;
+    const uint32_t buf = (I->geometry == GEOM_SLAB) ? I->cur : 0u;
+    const uint32_t off = I->cell_off[cell];
+    const uint32_t n = I->cell_off[cell + 1] - off;
+    const T* vx = reinterpret_cast<const T*>(I->vx[buf]) + off;
+    const T* vy = reinterpret_cast<const T*>(I->vy[buf]) + off;
+    const T* vz = reinterpret_cast<const T*>(I->vz[buf]) + off;
+    double s[3] = {0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        s[0] += (double)vx[i];
+        s[1] += (double)vy[i];
+        s[2] += (double)vz[i];
+    }
+    block_sum<3>(s, red);
+    const double inv = n ? 1.0 / (double)n : 0.0;
+    const double u0 = s[0] * inv, u1 = s[1] * inv, u2 = s[2] * inv;
+    double p[4] = {0, 0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double a = (double)vx[i], b = (double)vy[i], c = (double)vz[i];
+        const double dx = a - u0, dy = b - u1, dz = c - u2;
+        p[0] += dx * dx;
+        p[1] += dy * dy;
+        p[2] += dz * dz;
+        const double e = a * a + b * b + c * c;
+        p[3] += e * e;
+    }
+    block_sum<4>(p, red);
+    if (threadIdx.x == 0) {
+        double* o = I->moments + 9ull * cell;
+        o[0] = (double)n * I->rho_factor;
+        o[1] = u0;
+        o[2] = u1;
+        o[3] = u2;
+        o[4] = (p[0] + p[1] + p[2]) * inv / 3.0;
+        o[5] = p[0] * inv;
+        o[6] = p[1] * inv;
+        o[7] = p[2] * inv;
+        o[8] = p[3] * inv;
+    }
+}
+
+// End of a step: advance the step counter, flip the slab buffer.
+__global__ void k_advance(InstDev* const* __restrict__ insts, uint32_t n_inst)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    InstDev* I = insts[i];
+    I->step += 1u;
+    if (I->geometry == GEOM_SLAB) I->cur ^= 1u;
+}
+
+template __global__ void k_hist<float>(InstDev*);
+template __global__ void k_hist<double>(InstDev*);
+template __global__ void k_scatter<float>(InstDev*);
+template __global__ void k_scatter<double>(InstDev*);
+template __global__ void k_moments<float>(const CellRef*, uint32_t);
+template __global__ void k_moments<double>(const CellRef*, uint32_t);
+
+}  // namespace trmc

@@ -1,0 +1,567 @@
+// runtime.hip -- host runtime of libtrmc: validation, workspace layout, the
+// instance table, the work lists of the collision kernel and the launch
+// sequence of one step (transport + sort per slab, then one collision launch per
+// precision over every active cell, then the device-side step advance).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/trmc.h"
+#include "trmc_internal.h"
+
+namespace trmc {
+template <typename T>
+__global__ void k_collide(const CellRef*, uint32_t, uint32_t);
+template <typename T>
+__global__ void k_hist(InstDev*);
+__global__ void k_scan_tiles(InstDev*);
+__global__ void k_scan_cells(InstDev*);
+template <typename T>
+__global__ void k_scatter(InstDev*);
+template <typename T>
+__global__ void k_moments(const CellRef*, uint32_t);
+__global__ void k_advance(InstDev* const*, uint32_t);
+}  // namespace trmc
+
+using namespace trmc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t al(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+uint32_t sort_tile_h(uint32_t n_cells)
+{
+    uint32_t t = 4u * n_cells;
+    t = (t + 1023u) & ~1023u;
+    return t < kSortTile ? kSortTile : t;
+}
+
+struct Layout {
+    size_t inst, refs, eps, off, mstate, stats, mom, hist, bx, bvx, bvy, bvz, scratch, total;
+    uint32_t n_tiles;
+};
+
+Layout layout_of(const trmc_desc& d)
+{
+    Layout L{};
+    const size_t sz = d.precision == TRMC_FP64 ? 8 : 4;
+    const uint32_t nc = d.geometry == TRMC_SLAB1D ? d.n_cells : 1u;
+    const uint64_t n = d.n_particles;
+    size_t p = 0;
+    L.inst = p;    p += al(sizeof(InstDev));
+    L.refs = p;    p += al(sizeof(CellRef) * nc);
+    L.eps = p;     p += al(sizeof(double) * nc);
+    L.off = p;     p += al(sizeof(uint32_t) * (nc + 1));
+    L.mstate = p;  p += al(sizeof(uint32_t) * nc);
+    L.stats = p;   p += al(sizeof(CellStats) * nc);
+    L.mom = p;     p += al(sizeof(double) * 9 * nc);
+    L.n_tiles = 0;
+    if (d.geometry == TRMC_SLAB1D) {
+        const uint32_t tile = sort_tile_h(nc);
+        L.n_tiles = (uint32_t)((n + tile - 1) / tile);
+        L.hist = p;  p += al(sizeof(uint32_t) * (size_t)L.n_tiles * nc);
+        L.bx = p;    p += al(sz * n);
+        L.bvx = p;   p += al(sz * n);
+        L.bvy = p;   p += al(sz * n);
+        L.bvz = p;   p += al(sz * n);
+    }
+    L.scratch = p;
+    p += al(scratch_bpp((uint32_t)sz) * n + scratch_cpc((uint32_t)sz) * nc);
+    L.total = p;
+    return L;
+}
+
+int validate(const trmc_desc* d)
+{
+    if (!d || d->struct_size != sizeof(trmc_desc)) return TRMC_EINVAL;
+    if (d->geometry != TRMC_HOMOG && d->geometry != TRMC_SLAB1D) return TRMC_EINVAL;
+    if (d->precision != TRMC_FP64 && d->precision != TRMC_FP32_MIXED) return TRMC_EINVAL;
+    if (d->n_particles < 1 || d->n_particles > (1ull << 30)) return TRMC_EINVAL;
+    if (d->geometry == TRMC_HOMOG && d->n_cells != 1) return TRMC_EINVAL;
+    if (d->geometry == TRMC_SLAB1D && (d->n_cells < 1 || d->n_cells > kMaxSlabCells)) return TRMC_EINVAL;
+    if (!(d->length > 0.0) || !std::isfinite(d->length)) return TRMC_EINVAL;
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return TRMC_EINVAL;
+    if (!(d->particle_weight > 0.0) || !std::isfinite(d->particle_weight)) return TRMC_EINVAL;
+    const uint32_t nc = d->geometry == TRMC_SLAB1D ? d->n_cells : 1u;
+    if (d->eps_cells) {
+        for (uint32_t c = 0; c < nc; ++c)
+            if (!(d->eps_cells[c] > 0.0)) return TRMC_EINVAL;
+    } else if (!(d->eps > 0.0)) {
+        return TRMC_EINVAL;
+    }
+    if (!(d->alpha >= 0.0 && d->alpha <= 1.0)) return TRMC_EINVAL;
+    if (d->trunc > TRMC_ADAPTIVE) return TRMC_EINVAL;
+    if (d->m_cap < 1 || d->m_cap > kMaxDepth) return TRMC_EINVAL;
+    if (d->m_init < 1 || d->m_init > d->m_cap) return TRMC_EINVAL;
+    if (d->trunc == TRMC_ADAPTIVE && !(d->delta1 > 0.0 && d->delta1 < d->delta2)) return TRMC_EINVAL;
+    if (d->m_state0) {
+        for (uint32_t c = 0; c < nc; ++c)
+            if (d->m_state0[c] < 1 || d->m_state0[c] > d->m_cap) return TRMC_EINVAL;
+    }
+    return 0;
+}
+
+struct Slot {
+    bool active = false;
+    trmc_desc desc{};
+    trmc_particles user{};
+    unsigned char* ws = nullptr;
+    InstDev* dev = nullptr;
+    InstDev host{};
+    Layout lay{};
+    uint64_t steps = 0;  // steps enqueued since admission
+};
+
+}  // namespace
+
+struct trmc_ctx {
+    hipStream_t stream = nullptr;
+    unsigned char* ws = nullptr;
+    size_t ws_bytes = 0;
+    uint32_t max_inst = 0, max_cells = 0;
+    uint32_t* error = nullptr;
+    CellRef* work[2] = {nullptr, nullptr};  // [0] FP32, [1] FP64
+    uint32_t n_work[2] = {0, 0};
+    uint32_t lv_stride[2] = {2, 2};
+    InstDev** inst_ptrs = nullptr;
+    uint32_t n_active = 0;
+    uint32_t cells_used = 0;
+    std::vector<Slot> slots;
+    int sticky = 0;
+};
+
+namespace {
+
+size_t ctx_bytes(uint32_t max_inst, uint32_t max_cells)
+{
+    return al(sizeof(uint32_t)) + 2 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
+           al(sizeof(InstDev*) * std::max(1u, max_inst));
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? 0 : TRMC_EIO; }
+
+// Rebuild the device work lists (largest cells first) and the instance list.
+int rebuild_tables(trmc_ctx* c)
+{
+    std::vector<CellRef> w[2];
+    std::vector<std::pair<double, CellRef>> order[2];
+    std::vector<InstDev*> ptrs;
+    uint32_t stride[2] = {2, 2};
+    for (auto& s : c->slots) {
+        if (!s.active) continue;
+        ptrs.push_back(s.dev);
+        const int k = s.desc.precision == TRMC_FP64 ? 1 : 0;
+        const uint32_t nc = s.desc.geometry == TRMC_SLAB1D ? s.desc.n_cells : 1u;
+        const double per = (double)s.desc.n_particles / nc;
+        for (uint32_t cc = 0; cc < nc; ++cc) {
+            CellRef r{s.dev, cc, 0};
+            order[k].push_back({per, r});
+        }
+        stride[k] = std::max(stride[k], s.desc.m_cap + 2u);
+    }
+    for (int k = 0; k < 2; ++k) {
+        std::stable_sort(order[k].begin(), order[k].end(),
+                         [](const auto& a, const auto& b) { return a.first > b.first; });
+        for (auto& e : order[k]) w[k].push_back(e.second);
+        if (!w[k].empty()) {
+            hipError_t e = hipMemcpyAsync(c->work[k], w[k].data(), sizeof(CellRef) * w[k].size(),
+                                          hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) return TRMC_EIO;
+        }
+        c->n_work[k] = (uint32_t)w[k].size();
+        c->lv_stride[k] = stride[k];
+    }
+    if (!ptrs.empty()) {
+        hipError_t e = hipMemcpyAsync(c->inst_ptrs, ptrs.data(), sizeof(InstDev*) * ptrs.size(),
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return TRMC_EIO;
+    }
+    c->n_active = (uint32_t)ptrs.size();
+    // the host vectors die here: make the copies complete first
+    return hip_status(hipStreamSynchronize(c->stream));
+}
+
+int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned char* ws, size_t bytes,
+              uint32_t* slot_out, bool rebuild)
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    if (!b || !b->vx || !b->vy || !b->vz) return TRMC_EINVAL;
+    if (d->geometry == TRMC_SLAB1D && !b->x) return TRMC_EINVAL;
+    if (!ws || ((uintptr_t)ws & (kAlign - 1))) return TRMC_EINVAL;
+    const Layout L = layout_of(*d);
+    if (bytes < L.total) return TRMC_ENOMEM;
+    const uint32_t nc = d->geometry == TRMC_SLAB1D ? d->n_cells : 1u;
+    if (c->cells_used + nc > c->max_cells) return TRMC_ENOSPC;
+    uint32_t slot = UINT32_MAX;
+    for (uint32_t i = 0; i < c->slots.size(); ++i)
+        if (!c->slots[i].active) { slot = i; break; }
+    if (slot == UINT32_MAX) {
+        if (c->slots.size() >= c->max_inst) return TRMC_ENOSPC;
+        c->slots.emplace_back();
+        slot = (uint32_t)c->slots.size() - 1;
+    }
+    Slot& s = c->slots[slot];
+    s = Slot{};
+    s.desc = *d;
+    s.desc.eps_cells = nullptr;
+    s.desc.m_state0 = nullptr;
+    s.user = *b;
+    s.ws = ws;
+    s.lay = L;
+    s.dev = reinterpret_cast<InstDev*>(ws + L.inst);
+    InstDev& h = s.host;
+    const size_t sz = d->precision == TRMC_FP64 ? 8 : 4;
+    h.x[0] = b->x;
+    h.vx[0] = b->vx;
+    h.vy[0] = b->vy;
+    h.vz[0] = b->vz;
+    if (d->geometry == TRMC_SLAB1D) {
+        h.x[1] = ws + L.bx;
+        h.vx[1] = ws + L.bvx;
+        h.vy[1] = ws + L.bvy;
+        h.vz[1] = ws + L.bvz;
+    } else {
+        h.x[1] = b->x;
+        h.vx[1] = b->vx;
+        h.vy[1] = b->vy;
+        h.vz[1] = b->vz;
+    }
+    h.n = d->n_particles;
+    h.n_cells = nc;
+    h.geometry = d->geometry == TRMC_SLAB1D ? GEOM_SLAB : GEOM_HOMOG;
+    h.precision = d->precision == TRMC_FP64 ? PREC_FP64 : PREC_FP32;
+    h.trunc = d->trunc;
+    h.m_init = d->m_init;
+    h.m_cap = d->m_cap;
+    h.seed = d->seed;
+    h.uid = d->uid;
+    h.step = d->step0;
+    h.cur = 0;
+    h.n_tiles = L.n_tiles;
+    h.length = d->length;
+    h.dt = d->dt;
+    const double volume = d->geometry == TRMC_SLAB1D ? d->length / (double)nc : d->length;
+    h.rho_factor = d->particle_weight / volume;
+    h.alpha = d->alpha;
+    h.delta1 = d->delta1;
+    h.delta2 = d->delta2;
+    h.inv_dx = (double)nc / d->length;
+    h.eps_cells = reinterpret_cast<const double*>(ws + L.eps);
+    h.cell_off = reinterpret_cast<uint32_t*>(ws + L.off);
+    h.m_state = reinterpret_cast<uint32_t*>(ws + L.mstate);
+    h.stats = reinterpret_cast<CellStats*>(ws + L.stats);
+    h.moments = reinterpret_cast<double*>(ws + L.mom);
+    h.hist = d->geometry == TRMC_SLAB1D ? reinterpret_cast<uint32_t*>(ws + L.hist) : nullptr;
+    h.scratch = ws + L.scratch;
+    h.scratch_bpp = scratch_bpp((uint32_t)sz);
+    h.scratch_cpc = scratch_cpc((uint32_t)sz);
+    h.error = c->error;
+
+    std::vector<double> eps(nc);
+    std::vector<uint32_t> off(nc + 1, 0), ms(nc);
+    std::vector<CellRef> refs(nc);
+    for (uint32_t i = 0; i < nc; ++i) {
+        eps[i] = d->eps_cells ? d->eps_cells[i] : d->eps;
+        ms[i] = d->m_state0 ? d->m_state0[i] : d->m_init;
+        refs[i] = CellRef{s.dev, i, 0};
+    }
+    off[nc] = (uint32_t)d->n_particles;  // homogeneous: one cell [0, n); slab: set by the sort
+    hipError_t e = hipSuccess;
+    e = e == hipSuccess ? hipMemcpyAsync(ws + L.inst, &h, sizeof(InstDev), hipMemcpyHostToDevice, c->stream) : e;
+    e = e == hipSuccess ? hipMemcpyAsync(ws + L.refs, refs.data(), sizeof(CellRef) * nc, hipMemcpyHostToDevice,
+                                         c->stream) : e;
+    e = e == hipSuccess ? hipMemcpyAsync(ws + L.eps, eps.data(), sizeof(double) * nc, hipMemcpyHostToDevice,
+                                         c->stream) : e;
+    e = e == hipSuccess ? hipMemcpyAsync(ws + L.off, off.data(), sizeof(uint32_t) * (nc + 1),
+                                         hipMemcpyHostToDevice, c->stream) : e;
+    e = e == hipSuccess ? hipMemcpyAsync(ws + L.mstate, ms.data(), sizeof(uint32_t) * nc, hipMemcpyHostToDevice,
+                                         c->stream) : e;
+    e = e == hipSuccess ? hipMemsetAsync(ws + L.stats, 0, sizeof(CellStats) * nc, c->stream) : e;
+    e = e == hipSuccess ? hipStreamSynchronize(c->stream) : e;
+    if (e != hipSuccess) {
+        s.active = false;
+        return TRMC_EIO;
+    }
+    s.active = true;
+    c->cells_used += nc;
+    rc = rebuild ? rebuild_tables(c) : 0;
+    if (rc) {
+        s.active = false;
+        c->cells_used -= nc;
+        return rc;
+    }
+    *slot_out = slot;
+    return 0;
+}
+
+template <typename T>
+int launch_slab(trmc_ctx* c, Slot& s)
+{
+    const uint32_t nc = s.host.n_cells;
+    const uint32_t nt = s.lay.n_tiles;
+    if (nt == 0) return 0;
+    hipLaunchKernelGGL(k_hist<T>, dim3(nt), dim3(1024), sizeof(uint32_t) * nc, c->stream, s.dev);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((nc + 255) / 256), dim3(256), 0, c->stream, s.dev);
+    hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, c->stream, s.dev);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(nt), dim3(1024), sizeof(uint32_t) * nc, c->stream, s.dev);
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+int trmc_abi_version(void) { return TRMC_ABI_VERSION; }
+
+const char* trmc_strerror(int status)
+{
+    switch (status) {
+    case 0: return "success";
+    case TRMC_EINVAL: return "invalid argument (descriptor, buffer or slot)";
+    case TRMC_ENOMEM: return "workspace too small";
+    case TRMC_ENOSPC: return "no free instance slot or cell capacity";
+    case TRMC_EIO: return "HIP runtime error";
+    case TRMC_EOVERFLOW: return "a cell's collision trees exceeded the scratch capacity (cell left unchanged)";
+    default: return "unknown status";
+    }
+}
+
+int trmc_workspace_size(const trmc_desc* descs, uint32_t n_inst, size_t* bytes)
+{
+    if (!bytes || (n_inst && !descs)) return TRMC_EINVAL;
+    size_t total = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        int rc = validate(&descs[i]);
+        if (rc) return rc;
+        total += layout_of(descs[i]).total;
+    }
+    *bytes = total;
+    return 0;
+}
+
+int trmc_ctx_workspace_size(uint32_t max_instances, uint32_t max_cells, size_t* bytes)
+{
+    if (!bytes || max_instances == 0) return TRMC_EINVAL;
+    *bytes = ctx_bytes(max_instances, max_cells);
+    return 0;
+}
+
+int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trmc_particles* bufs,
+              void* workspace, size_t workspace_bytes, uint32_t max_instances, uint32_t max_cells,
+              void* hip_stream)
+{
+    if (!out || (n_inst && (!descs || !bufs)) || !workspace || max_instances < n_inst || max_instances == 0)
+        return TRMC_EINVAL;
+    if ((uintptr_t)workspace & (kAlign - 1)) return TRMC_EINVAL;
+    size_t need = ctx_bytes(max_instances, max_cells);
+    uint32_t cells = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        int rc = validate(&descs[i]);
+        if (rc) return rc;
+        need += layout_of(descs[i]).total;
+        cells += descs[i].geometry == TRMC_SLAB1D ? descs[i].n_cells : 1u;
+    }
+    if (cells > max_cells) return TRMC_ENOSPC;
+    if (workspace_bytes < need) return TRMC_ENOMEM;
+    trmc_ctx* c = new (std::nothrow) trmc_ctx();
+    if (!c) return TRMC_ENOMEM;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->ws = reinterpret_cast<unsigned char*>(workspace);
+    c->ws_bytes = workspace_bytes;
+    c->max_inst = max_instances;
+    c->max_cells = max_cells;
+    size_t p = 0;
+    c->error = reinterpret_cast<uint32_t*>(c->ws + p);
+    p += al(sizeof(uint32_t));
+    c->work[0] = reinterpret_cast<CellRef*>(c->ws + p);
+    p += al(sizeof(CellRef) * std::max(1u, max_cells));
+    c->work[1] = reinterpret_cast<CellRef*>(c->ws + p);
+    p += al(sizeof(CellRef) * std::max(1u, max_cells));
+    c->inst_ptrs = reinterpret_cast<InstDev**>(c->ws + p);
+    p += al(sizeof(InstDev*) * std::max(1u, max_instances));
+    if (hipMemsetAsync(c->error, 0, sizeof(uint32_t), c->stream) != hipSuccess) {
+        delete c;
+        return TRMC_EIO;
+    }
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        const size_t b = layout_of(descs[i]).total;
+        uint32_t slot;
+        int rc = admit_one(c, &descs[i], &bufs[i], c->ws + p, b, &slot, false);
+        if (rc) {
+            delete c;
+            return rc;
+        }
+        p += b;
+    }
+    int rc = rebuild_tables(c);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return 0;
+}
+
+int trmc_admit(trmc_ctx* c, const trmc_desc* desc, const trmc_particles* buf, void* workspace,
+               size_t workspace_bytes, uint32_t* slot)
+{
+    if (!c || !slot) return TRMC_EINVAL;
+    return admit_one(c, desc, buf, reinterpret_cast<unsigned char*>(workspace), workspace_bytes, slot, true);
+}
+
+int trmc_retire(trmc_ctx* c, uint32_t slot)
+{
+    if (!c || slot >= c->slots.size() || !c->slots[slot].active) return TRMC_EINVAL;
+    Slot& s = c->slots[slot];
+    s.active = false;
+    c->cells_used -= s.host.n_cells;
+    return rebuild_tables(c);
+}
+
+int trmc_step(trmc_ctx* c, uint32_t n_steps)
+{
+    if (!c) return TRMC_EINVAL;
+    if (c->sticky) return c->sticky;
+    for (uint32_t it = 0; it < n_steps; ++it) {
+        for (auto& s : c->slots) {
+            if (!s.active || s.host.geometry != GEOM_SLAB) continue;
+            int rc = s.host.precision == PREC_FP64 ? launch_slab<double>(c, s) : launch_slab<float>(c, s);
+            if (rc) return c->sticky = rc;
+        }
+        if (c->n_work[0])
+            hipLaunchKernelGGL(k_collide<float>, dim3(c->n_work[0]), dim3(kCollideThreads),
+                               sizeof(uint32_t) * 7 * c->lv_stride[0], c->stream, c->work[0], c->n_work[0],
+                               c->lv_stride[0]);
+        if (c->n_work[1])
+            hipLaunchKernelGGL(k_collide<double>, dim3(c->n_work[1]), dim3(kCollideThreads),
+                               sizeof(uint32_t) * 7 * c->lv_stride[1], c->stream, c->work[1], c->n_work[1],
+                               c->lv_stride[1]);
+        if (c->n_active)
+            hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, c->stream,
+                               c->inst_ptrs, c->n_active);
+        if (hipGetLastError() != hipSuccess) return c->sticky = TRMC_EIO;
+        for (auto& s : c->slots)
+            if (s.active) s.steps++;
+    }
+    return 0;
+}
+
+int trmc_sync(trmc_ctx* c)
+{
+    if (!c) return TRMC_EINVAL;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return c->sticky = TRMC_EIO;
+    uint32_t err = 0;
+    if (hipMemcpy(&err, c->error, sizeof err, hipMemcpyDeviceToHost) != hipSuccess) return c->sticky = TRMC_EIO;
+    if (err) {
+        const uint32_t zero = 0;
+        if (hipMemcpy(c->error, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return TRMC_EIO;
+        return TRMC_EOVERFLOW;
+    }
+    return c->sticky;
+}
+
+int trmc_state(trmc_ctx* c, uint32_t slot, trmc_particles* out)
+{
+    if (!c || !out || slot >= c->slots.size() || !c->slots[slot].active) return TRMC_EINVAL;
+    const Slot& s = c->slots[slot];
+    const uint32_t cur = s.host.geometry == GEOM_SLAB ? (uint32_t)(s.steps & 1u) : 0u;
+    out->x = s.host.x[cur];
+    out->vx = s.host.vx[cur];
+    out->vy = s.host.vy[cur];
+    out->vz = s.host.vz[cur];
+    return 0;
+}
+
+int trmc_moments(trmc_ctx* c, uint32_t slot, trmc_cell_moments* host_out, uint32_t cap)
+{
+    if (!c || !host_out || slot >= c->slots.size() || !c->slots[slot].active) return TRMC_EINVAL;
+    Slot& s = c->slots[slot];
+    const uint32_t nc = s.host.n_cells;
+    if (cap < nc) return TRMC_EINVAL;
+    const CellRef* refs = reinterpret_cast<const CellRef*>(s.ws + s.lay.refs);
+    if (s.host.precision == PREC_FP64)
+        hipLaunchKernelGGL(k_moments<double>, dim3(nc), dim3(256), 0, c->stream, refs, nc);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3(nc), dim3(256), 0, c->stream, refs, nc);
+    if (hipGetLastError() != hipSuccess) return c->sticky = TRMC_EIO;
+    std::vector<double> mom(9ull * nc);
+    std::vector<CellStats> st(nc);
+    std::vector<uint32_t> ms(nc);
+    hipError_t e = hipMemcpyAsync(mom.data(), s.host.moments, sizeof(double) * 9 * nc, hipMemcpyDeviceToHost,
+                                  c->stream);
+    e = e == hipSuccess ? hipMemcpyAsync(st.data(), s.host.stats, sizeof(CellStats) * nc, hipMemcpyDeviceToHost,
+                                         c->stream) : e;
+    e = e == hipSuccess ? hipMemcpyAsync(ms.data(), s.host.m_state, sizeof(uint32_t) * nc, hipMemcpyDeviceToHost,
+                                         c->stream) : e;
+    if (e != hipSuccess) return c->sticky = TRMC_EIO;
+    int rc = trmc_sync(c);
+    for (uint32_t i = 0; i < nc; ++i) {
+        trmc_cell_moments& o = host_out[i];
+        std::memset(&o, 0, sizeof o);
+        const double* m = &mom[9ull * i];
+        o.rho = m[0];
+        o.ux = m[1];
+        o.uy = m[2];
+        o.uz = m[3];
+        o.T = m[4];
+        o.Pxx = m[5];
+        o.Pyy = m[6];
+        o.Pzz = m[7];
+        o.M4 = m[8];
+        o.n = (uint32_t)llround(m[0] / s.host.rho_factor);
+        o.m_state = ms[i];
+        o.collisions = st[i].collisions;
+        o.dummies = st[i].dummies;
+        o.violations = st[i].violations;
+        o.work_collisions = st[i].work_collisions;
+        o.thermalized = st[i].n_th;
+        o.borrowed = st[i].borrowed;
+        o.m_eff = st[i].m_eff;
+        o.m_used = st[i].m_used;
+        o.attempts = st[i].attempts;
+        o.N0 = st[i].N0;
+        o.R0 = st[i].R0;
+        o.status = st[i].status;
+        o.q = st[i].q;
+        o.g = st[i].g;
+    }
+    return rc;
+}
+
+int trmc_read(trmc_ctx* c, uint32_t slot, void* x, void* vx, void* vy, void* vz, uint32_t* m_state,
+              uint32_t* step)
+{
+    if (!c || slot >= c->slots.size() || !c->slots[slot].active) return TRMC_EINVAL;
+    Slot& s = c->slots[slot];
+    trmc_particles cur{};
+    trmc_state(c, slot, &cur);
+    const size_t bytes = (s.host.precision == PREC_FP64 ? 8 : 4) * s.host.n;
+    int rc = trmc_sync(c);
+    hipError_t e = hipSuccess;
+    if (x && s.host.geometry == GEOM_SLAB) e = e == hipSuccess ? hipMemcpy(x, cur.x, bytes, hipMemcpyDeviceToHost) : e;
+    if (vx) e = e == hipSuccess ? hipMemcpy(vx, cur.vx, bytes, hipMemcpyDeviceToHost) : e;
+    if (vy) e = e == hipSuccess ? hipMemcpy(vy, cur.vy, bytes, hipMemcpyDeviceToHost) : e;
+    if (vz) e = e == hipSuccess ? hipMemcpy(vz, cur.vz, bytes, hipMemcpyDeviceToHost) : e;
+    if (m_state)
+        e = e == hipSuccess ? hipMemcpy(m_state, s.host.m_state, sizeof(uint32_t) * s.host.n_cells,
+                                        hipMemcpyDeviceToHost) : e;
+    if (step) *step = s.desc.step0 + (uint32_t)s.steps;
+    if (e != hipSuccess) return c->sticky = TRMC_EIO;
+    return rc;
+}
+
+int trmc_destroy(trmc_ctx* c)
+{
+    if (!c) return TRMC_EINVAL;
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    delete c;
+    return e == hipSuccess ? 0 : TRMC_EIO;
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+// trmc_device.h -- device helpers of libtrmc: counter-based random numbers, the
+// written exp(-x), the majorant grid, the keyed permutation of roles, and
+// deterministic block reductions.  gfx950, wave64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "trmc_internal.h"
+
+namespace trmc {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).  Key {seed, uid},
+// counter {index, tag << 24 | aux, cell, step}.
+// ---------------------------------------------------------------------------
+enum : uint32_t { TAG_SPLIT = 1, TAG_PERM = 2, TAG_TREE = 3, TAG_COLL = 4, TAG_MAXW = 5 };
+
+struct Key {
+    uint32_t seed, uid, cell, step;
+};
+
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo_a = 0xD2511F53u * c0, hi_a = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo_b = 0xCD9E8D57u * c2, hi_b = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi_b ^ c1 ^ k0;
+        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo_b;
+        c2 = n2;
+        c3 = lo_a;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint4 draw(const Key& k, uint32_t index, uint32_t tag, uint32_t aux)
+{
+    return philox10(index, (tag << 24) | (aux & 0xFFFFFFu), k.cell, k.step, k.seed, k.uid);
+}
+
+// 53-bit uniform in [0,1): the high word supplies the top 21 bits.
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo)
+{
+    const uint64_t b = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+    return (double)b * 0x1.0p-53;
+}
+// 24-bit uniform in [0,1): equals the top 24 bits of u53(w, .).
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 0x1.0p-24f; }
+
+// Sub-level choice j in {0..l-1} of collision c of level l (uniform, Alg. 4.1/4.3).
+__device__ __forceinline__ uint32_t tree_choice(const Key& k, uint32_t l, uint32_t c)
+{
+    const uint4 w = draw(k, c >> 2, TAG_TREE, l);
+    const uint32_t s = (c & 3u) == 0 ? w.x : (c & 3u) == 1 ? w.y : (c & 3u) == 2 ? w.z : w.w;
+    return __umulhi(s, l);
+}
+
+// ---------------------------------------------------------------------------
+// exp(-x) for x >= 0 by a fixed written algorithm (Cody-Waite reduction with a
+// two-part ln 2, degree-13 Taylor polynomial by Horner, scaling by 2^k), with
+// contraction off, so that q = exp(-mu dt/eps) has reproducible bits.
+// ---------------------------------------------------------------------------
+__device__ __noinline__ double exp_neg(double x)
+{
+#pragma clang fp contract(off)
+    const double head = 0x1.62e42p-1;
+    const double tail = 0x1.fdf473de6af28p-22;
+    const double inv_ln2 = 0x1.71547652b82fep+0;
+    if (!(x >= 0.0)) return x != x ? x : 1.0;
+    if (x > 746.0) return 0.0;
+    const double y = -x;
+    const double k = floor(y * inv_ln2 + 0.5);
+    const double r = (y - k * head) - k * tail;
+    double p = 1.0 / 6227020800.0;
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
+
+// Round a positive double up to 20 significant bits (grid of the VHS majorant).
+__device__ __forceinline__ double grid_up20(double g)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(g);
+    const uint64_t low = (1ull << 33) - 1ull;
+    if (b & low) b = (b | low) + 1ull;
+    return __longlong_as_double((long long)b);
+}
+
+// Iround of Alg. 4.2 (floor(y) + 1 with probability frac(y)), contraction off.
+__device__ __noinline__ uint32_t iround_prod(double q, uint32_t rem, double u)
+{
+#pragma clang fp contract(off)
+    const double y = q * (double)rem;
+    const double f = floor(y);
+    const uint32_t k = (uint32_t)f + (u < y - f ? 1u : 0u);
+    return k < rem ? k : rem;  // q <= 1 keeps k <= rem; the bound only guards bad input
+}
+
+// ---------------------------------------------------------------------------
+// Keyed permutation of roles: 6-round balanced Feistel network on b bits,
+// b = smallest even number >= max(8, ceil(log2 n)), cycle walking into [0, n).
+// Round i keys with k[i & 3] ^ (i * 0x9E3779B9); round function = MurmurHash3
+// 32-bit finalizer.  perm_inverse(s) returns the role index of slot s.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t perm_half(uint32_t n)
+{
+    uint32_t b = (n <= 1u) ? 0u : 32u - __clz(n - 1u);  // ceil(log2 n)
+    b = b < 8u ? 8u : b;
+    b += b & 1u;
+    return b >> 1;
+}
+
+__device__ __forceinline__ uint32_t feistel_dec(uint32_t y, uint32_t half, uint4 k)
+{
+    const uint32_t mask = (half >= 32u) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+    uint32_t L = y >> half, R = y & mask;
+    const uint32_t kk[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        const uint32_t rk = kk[i & 3] ^ ((uint32_t)i * 0x9E3779B9u);
+        // forward: (L, R) -> (R, L ^ F(R ^ rk)); inverse below
+        const uint32_t pl = R ^ (fmix32(L ^ rk) & mask);
+        const uint32_t pr = L;
+        L = pl;
+        R = pr;
+    }
+    return (L << half) | R;
+}
+
+__device__ __forceinline__ uint32_t perm_inverse(uint32_t s, uint32_t n, uint32_t half, uint4 k)
+{
+    uint32_t y = feistel_dec(s, half, k);
+    while (y >= n) y = feistel_dec(y, half, k);
+    return y;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed butterfly inside a wave, then waves in
+// order).  `red` holds kCollideThreads/64 * K doubles of LDS.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+        v[k] = a;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double a = 0.0;
+        for (int w = 0; w < nw; ++w) a += red[w * K + k];
+        v[k] = a;
+    }
+}
+
+__device__ __forceinline__ double block_max(double v, double* red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double a = red[0];
+    for (int w = 1; w < nw; ++w) a = fmax(a, red[w]);
+    return a;
+}
+
+template <int K>
+__device__ __forceinline__ void block_sum_u64(unsigned long long (&v)[K], unsigned long long* red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        unsigned long long a = v[k];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+        v[k] = a;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        unsigned long long a = 0;
+        for (int w = 0; w < nw; ++w) a += red[w * K + k];
+        v[k] = a;
+    }
+}
+
+}  // namespace trmc

@@ -1,0 +1,73 @@
+// trmc_internal.h -- device-side tables shared by the host runtime and the kernels
+// of libtrmc (private to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trmc {
+
+enum : uint32_t { GEOM_HOMOG = 1, GEOM_SLAB = 2 };
+enum : uint32_t { PREC_FP64 = 1, PREC_FP32 = 2 };
+enum : uint32_t { TRUNC_NATURAL = 0, TRUNC_FIXED = 1, TRUNC_ADAPTIVE = 2 };
+enum : uint32_t { CELL_OVERFLOW = 1u };
+
+constexpr uint32_t kMaxDepth = 2048;     // largest m_cap accepted
+constexpr uint32_t kMaxSlabCells = 12288;  // LDS histogram of the sort
+constexpr uint32_t kSortTile = 4096;     // particles per tile of the counting sort
+constexpr uint32_t kCollideThreads = 256;
+
+// Counters of one cell's last collision step.
+struct CellStats {
+    uint32_t n, N0, m_eff, m_used, attempts, R0, n_th, borrowed, folds, status;
+    unsigned long long collisions, dummies, violations, work_collisions;
+    double q, g, E1;
+};
+
+// One instance, resident in its workspace.  Kernels read parameters from here;
+// the step counter and the current slab buffer are advanced on the device so
+// that a captured sequence of launches can be replayed step after step.
+struct InstDev {
+    void* x[2];
+    void* vx[2];
+    void* vy[2];
+    void* vz[2];
+    uint64_t n;
+    uint32_t n_cells, geometry, precision, trunc;
+    uint32_t m_init, m_cap, seed, uid;
+    uint32_t step, cur;     // next step index; slab: buffer holding the state
+    uint32_t n_tiles, pad0;
+    double length, dt, rho_factor, alpha, delta1, delta2, inv_dx;
+    const double* eps_cells;  // [n_cells]
+    uint32_t* cell_off;       // [n_cells + 1]
+    uint32_t* m_state;        // [n_cells]
+    CellStats* stats;         // [n_cells]
+    double* moments;          // [n_cells][9]
+    uint32_t* hist;           // slab: [n_tiles][n_cells] tile histograms, then tile bases
+    unsigned char* scratch;   // collision scratch
+    uint64_t scratch_bpp;     // scratch bytes per particle
+    uint64_t scratch_cpc;     // scratch bytes per cell
+    uint32_t* error;          // context error word
+};
+
+// One work item of the collision kernel: a cell of an instance.
+struct CellRef {
+    InstDev* inst;
+    uint32_t cell;
+    uint32_t pad;
+};
+
+// Collision capacity of a cell with n particles (trees beyond it are flagged).
+__host__ __device__ inline uint64_t coll_cap(uint64_t n) { return 4ull * n + 256ull; }
+__host__ __device__ inline uint64_t align16(uint64_t b) { return (b + 15ull) & ~15ull; }
+
+// Per-cell scratch regions: role[n] u32 | leaf[3][n] | fin[3][n] | j[cap] u32 |
+// rA[cap] u32 | rB[cap] u32 | out[3][2 cap], with elements of `sz` bytes.  The
+// region of cell c starts at bpp * offset(c) + cpc * c, which never overlaps the
+// next one because its size is at most bpp * n + cpc.
+__host__ __device__ inline uint64_t scratch_bpp(uint32_t sz) { return align16(52ull + 30ull * sz); }
+__host__ __device__ inline uint64_t scratch_cpc(uint32_t sz)
+{
+    return ((256ull * (12ull + 6ull * sz) + 195ull + 255ull) / 256ull) * 256ull;
+}
+
+}  // namespace trmc

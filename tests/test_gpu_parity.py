@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+FP64: integer work (split sizes, tree counts, leaves, thermalized counts, cell
+counts and the sorted order) must be identical; particle trajectories must agree
+to 1e-12 relative (|dv| / sqrt(T_cell) and |dx| / dx).  FP32-mixed is compared
+in the statistical tests.  Every case prints its name before touching the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+INT_FIELDS = [("N0", "N0"), ("m_eff", "m_eff"), ("R0", "R0"), ("thermalized", "n_th"), ("borrowed", "borrowed"),
+              ("collisions", "collisions"), ("dummies", "dummies"), ("attempts", "attempts"),
+              ("m_used", "m_used"), ("m_state", "m_state_after")]
+
+
+@pytest.fixture(scope="module")
+def trmc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm GPU"
+    import paper_1009_2768_amd as T
+    T.load()
+    return T
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(T, insts, arrays, steps):
+    parts = [T.device_particles(a["vx"], a["vy"], a["vz"], a.get("x"), i.precision) for i, a in zip(insts, arrays)]
+    ctx = T.Context(insts, parts)
+    ctx.step(steps)
+    ctx.sync()
+    res = [(ctx.read(k), ctx.moments(k)) for k in range(len(insts))]
+    ctx.close()
+    return res
+
+
+def oracle_of(orc, gi, a):
+    kw = dict(seed=gi.seed, uid=gi.uid, dt=gi.dt, eps=gi.eps, alpha=gi.alpha, trunc=gi.trunc, m_init=gi.m_init,
+              m_cap=gi.m_cap, delta1=gi.delta1, delta2=gi.delta2, length=gi.length, weight=gi.particle_weight,
+              step=gi.step0)
+    if gi.geometry == 2:
+        kw.update(geometry=orc.SLAB, n_cells=gi.n_cells, eps_cells=gi.eps_cells, x=a["x"])
+    return orc.Instance(a["vx"], a["vy"], a["vz"], **kw)
+
+
+def compare(orc_inst, got, mom, nc):
+    """Integers exact, trajectories within TOL."""
+    recs = orc_inst.last
+    for c in range(nc):
+        r = recs[c]
+        for gk, ok in INT_FIELDS:
+            g = int(mom[gk][c])
+            o = int(getattr(r, ok))
+            if gk == "m_state":
+                o = int(orc_inst.m_state[c])
+            assert g == o, f"cell {c}: {gk} gpu={g} oracle={o}"
+        assert int(mom["status"][c]) == 0
+    if orc_inst.geometry == 2:
+        np.testing.assert_array_equal(mom["n"], orc_inst.counts)
+        starts = np.concatenate([[0], np.cumsum(orc_inst.counts.astype(np.int64))]).astype(np.int64)
+    else:
+        starts = np.array([0, orc_inst.n], dtype=np.int64)
+    worst = 0.0
+    for c in range(nc):
+        a, b = starts[c], starts[c + 1]
+        if b - a == 0:
+            continue
+        ov = np.stack([orc_inst.vx[a:b], orc_inst.vy[a:b], orc_inst.vz[a:b]], 1)
+        gv = np.stack([got["vx"][a:b], got["vy"][a:b], got["vz"][a:b]], 1).astype(np.float64)
+        T = max(ov.var(0).sum() / 3.0, 1e-300)
+        worst = max(worst, float(np.abs(gv - ov).max() / math.sqrt(T)))
+    assert worst <= TOL, f"max |dv|/sqrt(T) = {worst:.3e}"
+    if orc_inst.geometry == 2:
+        dx = orc_inst.length / orc_inst.n_cells
+        err = float(np.abs(got["x"].astype(np.float64) - orc_inst.x).max() / dx)
+        assert err <= TOL, f"max |dx|/dx = {err:.3e}"
+    return worst
+
+
+def homog(T, n, eps, alpha=0.0, trunc=0, m_init=2, m_cap=64, init="bkw", uid=0, seed=0, dt=0.05, stream=0):
+    if init == "bkw":
+        vx, vy, vz = W.bkw(n, 0.6, seed=seed, stream=stream)
+    else:
+        vx, vy, vz = W.bimaxwellian(n, seed=seed, stream=stream)
+    inst = T.Instance(n_particles=n, eps=eps, alpha=alpha, trunc=trunc, m_init=m_init, m_cap=m_cap, uid=uid,
+                      seed=seed, dt=dt, precision=T.FP64)
+    return inst, {"vx": vx, "vy": vy, "vz": vz}
+
+
+@pytest.mark.parametrize("eps,trunc,steps", [(1.0, 0, 4), (0.1, 0, 3), (0.1, 2, 4), (1.0, 1, 3)])
+def test_homogeneous_maxwell_fp64(trmc, orc, eps, trunc, steps):
+    say("homog maxwell fp64", eps, trunc, steps)
+    inst, a = homog(trmc, 10000, eps, trunc=trunc, m_init=3, m_cap=2048 if trunc == 0 else 64)
+    (got, mom), = run_gpu(trmc, [inst], [a], steps)
+    o = oracle_of(orc, inst, a)
+    o.run(steps)
+    compare(o, got, mom, 1)
+
+
+@pytest.mark.parametrize("eps,trunc", [(0.05, 2), (0.5, 2), (0.01, 1), (2.0, 0)])
+def test_homogeneous_hard_spheres_fp64(trmc, orc, eps, trunc):
+    say("homog VHS fp64", eps, trunc)
+    inst, a = homog(trmc, 3000, eps, alpha=1.0, trunc=trunc, m_init=2, m_cap=64, init="bimax", uid=7)
+    (got, mom), = run_gpu(trmc, [inst], [a], 4)
+    o = oracle_of(orc, inst, a)
+    o.run(4)
+    compare(o, got, mom, 1)
+    assert o.last[0].dummies > 0 or o.last[0].collisions == 0 or eps > 1
+
+
+def test_natural_depth_c1_small_eps(trmc, orc):
+    """eps = 0.01: deep natural trees (hundreds of levels, folding)."""
+    say("homog maxwell natural eps=0.01")
+    inst, a = homog(trmc, 10000, 0.01, trunc=0, m_cap=2048)
+    (got, mom), = run_gpu(trmc, [inst], [a], 1)
+    o = oracle_of(orc, inst, a)
+    o.run(1)
+    compare(o, got, mom, 1)
+    assert o.last[0].m_eff > 100
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 17, 64, 257, 1000])
+def test_small_cells_and_folding(trmc, orc, n):
+    say("small cell", n)
+    insts, arrays = [], []
+    for k, (eps, alpha) in enumerate([(0.005, 0.0), (0.05, 1.0), (1.0, 0.0), (0.02, 1.0)]):
+        inst, a = homog(trmc, n, eps, alpha=alpha, trunc=2, m_init=4, m_cap=64, uid=100 + k, stream=k,
+                        init="bimax")
+        insts.append(inst)
+        arrays.append(a)
+    res = run_gpu(trmc, insts, arrays, 3)
+    for inst, a, (got, mom) in zip(insts, arrays, res):
+        o = oracle_of(orc, inst, a)
+        o.run(3)
+        if n < 2:
+            np.testing.assert_array_equal(got["vx"], a["vx"])
+            continue
+        compare(o, got, mom, 1)
+
+
+def test_batched_mixed_instances_each_match_alone(trmc, orc):
+    say("batch of mixed homogeneous instances")
+    N, eps, alpha, init = W.batched_homogeneous(24, seed=3, n_min=64, n_max=4096)
+    insts, arrays = [], []
+    for i in range(24):
+        inst, a = homog(trmc, int(N[i]), float(eps[i]), alpha=float(alpha[i]), trunc=2, m_init=2, m_cap=64,
+                        uid=i, init="bkw" if init[i] == 0 else "bimax", stream=i)
+        insts.append(inst)
+        arrays.append(a)
+    res = run_gpu(trmc, insts, arrays, 3)
+    for inst, a, (got, mom) in zip(insts, arrays, res):
+        o = oracle_of(orc, inst, a)
+        o.run(3)
+        compare(o, got, mom, 1)
+
+
+def _sod_inst(T, nc, ppl, ppr, eps=0.01, trunc=2, seed=4, precision=None):
+    x, vx, vy, vz, w = W.sod(nc, ppl, ppr, seed=seed)
+    inst = T.Instance(n_particles=len(x), geometry=T.SLAB1D, n_cells=nc, dt=W.sod_dt(1.0, nc), eps=eps,
+                      alpha=1.0, trunc=trunc, m_init=2, m_cap=64, particle_weight=w, uid=11, seed=seed,
+                      precision=precision or T.FP64)
+    return inst, {"x": x, "vx": vx, "vy": vy, "vz": vz}
+
+
+@pytest.mark.parametrize("nc,ppl,ppr,steps", [(20, 80, 10, 5), (200, 60, 8, 3), (7, 1500, 190, 2)])
+def test_slab_fp64(trmc, orc, nc, ppl, ppr, steps):
+    say("slab fp64", nc, ppl, ppr, steps)
+    inst, a = _sod_inst(trmc, nc, ppl, ppr)
+    (got, mom), = run_gpu(trmc, [inst], [a], steps)
+    o = oracle_of(orc, inst, a)
+    o.run(steps)
+    compare(o, got, mom, nc)
+
+
+def test_slab_unsorted_input_and_eps_profile(trmc, orc):
+    say("slab unsorted input, eps(x)")
+    inst, a = _sod_inst(trmc, 50, 40, 6)
+    perm = np.random.default_rng(0).permutation(inst.n_particles)
+    a = {k: v[perm] for k, v in a.items()}
+    inst.eps_cells = W.transition_eps(50)
+    (got, mom), = run_gpu(trmc, [inst], [a], 3)
+    o = oracle_of(orc, inst, a)
+    o.run(3)
+    compare(o, got, mom, 50)
+
+
+def test_moments_match_oracle(trmc, orc):
+    say("moments")
+    inst, a = homog(trmc, 5000, 0.3, alpha=1.0, trunc=2, init="bimax", uid=3)
+    (got, mom), = run_gpu(trmc, [inst], [a], 2)
+    o = oracle_of(orc, inst, a)
+    o.run(2)
+    m = o.moments()[0]
+    for k, key in enumerate(["rho", "ux", "uy", "uz", "T", "Pxx", "Pyy", "Pzz", "M4"]):
+        assert mom[key][0] == pytest.approx(m[k], rel=1e-12, abs=1e-13), key
