@@ -40,7 +40,9 @@
  *       into the remainder;
  *   R7  the Maxwellian remainder is sampled by Box-Muller and then affinely
  *       rescaled to the removed particles' momentum and energy (exact
- *       conservation); a remainder of at most one particle is left unchanged;
+ *       conservation); a remainder of at most one particle is left unchanged,
+ *       and a normal sample with zero spread (not reachable in practice) puts
+ *       the remainder at the removed mean;
  *   R8  adaptive depth (Sec. 4.3) uses S = P_xx per unit mass, the analytic
  *       Maxwellian estimate for the thermalized part, halving (at least 1) below
  *       delta1, keeping between delta1 and delta2, and recomputing from the
@@ -529,7 +531,7 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
                     wth[t].y = ur.y + a * (wth[t].y - zm.y);
                     wth[t].z = ur.z + a * (wth[t].z - zm.z);
                 } else {
-                    wth[t] = v[therm_slot(&ro, t)];
+                    wth[t] = ur; /* degenerate normal sample: the removed mean (momentum kept) */
                 }
             }
         } else {

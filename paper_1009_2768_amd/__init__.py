@@ -56,7 +56,7 @@ class Instance:
         d.length, d.dt = self.length, self.dt
         w = self.particle_weight
         if w is None:
-            w = self.length / self.n_particles
+            w = self.length / max(1, self.n_particles)
         d.particle_weight = w
         d.eps, d.alpha = self.eps, self.alpha
         d.trunc, d.m_init, d.m_cap, d.step0 = self.trunc, self.m_init, self.m_cap, self.step0

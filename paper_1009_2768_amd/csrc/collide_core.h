@@ -1,0 +1,718 @@
+// collide_core.h -- building blocks of the per-cell TRMC-R collision step
+// shared by the whole-cell kernel (small cells, slab cells) and the tiled
+// pipeline (large homogeneous cells).  A "group" of G threads (one wave, or a
+// whole workgroup) owns one cell in the per-cell phases.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "trmc_device.h"
+#include "trmc_internal.h"
+
+namespace trmc {
+
+template <typename T>
+struct Vec3 {
+    T x, y, z;
+};
+
+// ---------------------------------------------------------------------------
+// Group primitives: a group of G threads works on one cell.  G = 64 is one wave
+// (wave-synchronous: LDS traffic ordered by fences, no workgroup barrier);
+// G = workgroup size uses workgroup barriers.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ void gsync()
+{
+    if constexpr (G == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Sum over the group; every thread receives the total.  Fixed order: butterfly
+// inside each wave, then the waves in order.  `red` holds (G/64) * K doubles.
+template <int G, int K>
+__device__ __forceinline__ void gsum(double (&v)[K], double* red)
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+        v[k] = a;
+    }
+    if constexpr (G > 64) {
+        const int lane = threadIdx.x & 63, wave = (threadIdx.x % G) >> 6;
+        gsync<G>();
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+        }
+        gsync<G>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double a = 0.0;
+            for (int w = 0; w < G / 64; ++w) a += red[w * K + k];
+            v[k] = a;
+        }
+    }
+}
+
+template <int G>
+__device__ __forceinline__ double gmax(double v, double* red)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if constexpr (G > 64) {
+        const int lane = threadIdx.x & 63, wave = (threadIdx.x % G) >> 6;
+        gsync<G>();
+        if (lane == 0) red[wave] = v;
+        gsync<G>();
+        double a = red[0];
+        for (int w = 1; w < G / 64; ++w) a = fmax(a, red[w]);
+        v = a;
+    }
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t gsum_u32(uint32_t v, uint32_t* red)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if constexpr (G > 64) {
+        const int lane = threadIdx.x & 63, wave = (threadIdx.x % G) >> 6;
+        gsync<G>();
+        if (lane == 0) red[wave] = v;
+        gsync<G>();
+        uint32_t a = 0;
+        for (int w = 0; w < G / 64; ++w) a += red[w];
+        v = a;
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------------------
+// Arithmetic of one collision and of the Maxwellian samples.
+// FP64: library sqrt/sin/cos/log.  FP32: hardware transcendentals, with the
+// angle in revolutions (sin(2 pi u) directly), log2 and sqrt.
+// ---------------------------------------------------------------------------
+// Collision draws: FP64 takes the high bits from block 0 and the low bits from
+// block 1; FP32 takes block 0 only (its uniforms are the top 24 bits of FP64's).
+template <typename T>
+struct Draws;
+
+template <>
+struct Draws<double> {
+    static __device__ __forceinline__ void coll(const Key& k, uint32_t l, uint32_t c, double& xi1, double& xi2,
+                                                double& xacc)
+    {
+        const uint4 b0 = draw(k, c, TAG_COLL, l);
+        const uint4 b1 = draw(k, c, TAG_COLL, l | (1u << 20));
+        xi1 = u53(b0.x, b1.x);
+        xi2 = u53(b0.y, b1.y);
+        xacc = u53(b0.z, b1.z);
+    }
+    static __device__ __forceinline__ void sincos2pi(double u, double& s, double& c)
+    {
+        const double a = 6.283185307179586 * u;
+        s = sin(a);
+        c = cos(a);
+    }
+    static __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); }
+    static __device__ __forceinline__ double pow_(double a, double b) { return pow(a, b); }
+    static __device__ __forceinline__ Vec3<double> normals(const Key& k, uint32_t t)
+    {
+        const uint4 b0 = draw(k, t, TAG_MAXW, 0);
+        const uint4 b1 = draw(k, t, TAG_MAXW, 1);
+        const double u0 = u53(b0.x, b1.x), u1 = u53(b0.y, b1.y), u2 = u53(b0.z, b1.z), u3 = u53(b0.w, b1.w);
+        const double r1 = sqrt(-2.0 * log(1.0 - u0));
+        const double r2 = sqrt(-2.0 * log(1.0 - u2));
+        double s1, c1, s2, c2;
+        sincos2pi(u1, s1, c1);
+        sincos2pi(u3, s2, c2);
+        return Vec3<double>{r1 * c1, r1 * s1, r2 * c2};
+    }
+};
+
+template <>
+struct Draws<float> {
+    static __device__ __forceinline__ void coll(const Key& k, uint32_t l, uint32_t c, float& xi1, float& xi2,
+                                                float& xacc)
+    {
+        const uint4 b0 = draw(k, c, TAG_COLL, l);
+        xi1 = u24(b0.x);
+        xi2 = u24(b0.y);
+        xacc = u24(b0.z);
+    }
+    static __device__ __forceinline__ void sincos2pi(float u, float& s, float& c)
+    {
+        s = __builtin_amdgcn_sinf(u);  // sin(2 pi u)
+        c = __builtin_amdgcn_cosf(u);
+    }
+    static __device__ __forceinline__ float sqrt_(float a) { return __builtin_amdgcn_sqrtf(a); }
+    static __device__ __forceinline__ float pow_(float a, float b)
+    {
+        return a > 0.0f ? __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(a)) : 0.0f;
+    }
+    static __device__ __forceinline__ Vec3<float> normals(const Key& k, uint32_t t)
+    {
+        const uint4 b0 = draw(k, t, TAG_MAXW, 0);
+        // -2 ln(1-u) = -2 ln2 log2(1-u); 1 - u >= 2^-24
+        const float r1 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(1.0f - u24(b0.x)));
+        const float r2 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(1.0f - u24(b0.z)));
+        float s1, c1, s2, c2;
+        sincos2pi(u24(b0.y), s1, c1);
+        sincos2pi(u24(b0.w), s2, c2);
+        return Vec3<float>{r1 * c1, r1 * s1, r2 * c2};
+    }
+};
+
+// One collision of eq. (Maxwell_coll-r); dummy (outputs = inputs) unless
+// xi_acc * g < |q|^alpha.  Returns 1 if real.
+template <typename T>
+__device__ __forceinline__ int collide(const Vec3<T>& a, const Vec3<T>& b, T xi1, T xi2, T xacc, T alpha, T g,
+                                       Vec3<T>& oa, Vec3<T>& ob, uint32_t& viol)
+{
+    const T qx = a.x - b.x, qy = a.y - b.y, qz = a.z - b.z;
+    const T qn = Draws<T>::sqrt_(qx * qx + qy * qy + qz * qz);
+    if (alpha != T(0)) {
+        const T s = (alpha == T(1)) ? qn : Draws<T>::pow_(qn, alpha);
+        viol += (s > g) ? 1u : 0u;
+        if (!(xacc * g < s)) {
+            oa = a;
+            ob = b;
+            return 0;
+        }
+    }
+    const T ct = T(2) * xi1 - T(1);
+    const T st2 = T(1) - ct * ct;
+    const T st = Draws<T>::sqrt_(st2 > T(0) ? st2 : T(0));
+    T sp, cp;
+    Draws<T>::sincos2pi(xi2, sp, cp);
+    const T h = T(0.5) * qn;
+    const T sx = cp * st, sy = sp * st, sz = ct;
+    const T cx = T(0.5) * (a.x + b.x), cy = T(0.5) * (a.y + b.y), cz = T(0.5) * (a.z + b.z);
+    oa.x = cx + h * sx;
+    oa.y = cy + h * sy;
+    oa.z = cz + h * sz;
+    ob.x = cx - h * sx;
+    ob.y = cy - h * sy;
+    ob.z = cz - h * sz;
+    return 1;
+}
+
+// Scalars shared by a group.
+struct CellShared {
+    double mean[3];
+    double Sn, q, g, ur[3], a_th, zbar[3], E1;
+    uint32_t me, split_rem, R0, N0, borrowed, n_th, folds, m, attempts, decision, overflow;
+    unsigned long long ncoll, work;
+    uint32_t dummies, viol;
+};
+
+// Level arrays of a group, lv_stride = m_cap + 2 entries each (dynamic LDS).
+struct Levels {
+    uint32_t *N, *Rtot, *C, *outoff, *run;
+};
+
+// LDS of one group (besides its level arrays).
+template <int G>
+struct GroupLds {
+    CellShared sh;
+    double red[(G / 64) * 12];
+    uint32_t redu[(G / 64) * 2];
+    uint32_t wcnt[G / 64][64];
+    uint32_t wpre[G / 64][64];
+    uint16_t jbuf[G];
+};
+
+
+// Pointers into one cell's scratch region (layout in trmc_internal.h).
+template <typename T>
+struct CellMem {
+    uint32_t* role;  // [n] role index of each slot
+    T* leaf;         // [3][n] leaves by leaf rank
+    T* fin;          // [3][n] finals by destination slot
+    uint32_t* jarr;  // [cap] sub-level choice of each collision
+    uint32_t* rA;    // [cap] rank of request A at level j
+    uint32_t* rB;    // [cap] rank of request B at level l-1-j
+    T* outv;         // [3][2 cap] outputs taken by requests
+    uint64_t cap, ocap;
+    __device__ __forceinline__ void init(const InstDev* I, uint32_t off, uint32_t cell, uint32_t n)
+    {
+        cap = coll_cap(n);
+        ocap = 2ull * cap;
+        unsigned char* base = I->scratch + I->scratch_bpp * (uint64_t)off + I->scratch_cpc * (uint64_t)cell;
+        role = reinterpret_cast<uint32_t*>(base);
+        base += align16(4ull * n);
+        leaf = reinterpret_cast<T*>(base);
+        base += 3 * align16(sizeof(T) * (uint64_t)n);
+        fin = reinterpret_cast<T*>(base);
+        base += 3 * align16(sizeof(T) * (uint64_t)n);
+        jarr = reinterpret_cast<uint32_t*>(base);
+        base += align16(4ull * cap);
+        rA = reinterpret_cast<uint32_t*>(base);
+        base += align16(4ull * cap);
+        rB = reinterpret_cast<uint32_t*>(base);
+        base += align16(4ull * cap);
+        outv = reinterpret_cast<T*>(base);
+    }
+};
+
+__device__ __forceinline__ Levels levels_at(uint32_t* p, uint32_t stride)
+{
+    Levels L;
+    L.N = p;
+    L.Rtot = L.N + stride;
+    L.C = L.Rtot + stride;
+    L.outoff = L.C + stride;
+    L.run = L.outoff + stride;
+    return L;
+}
+
+// Majorant, relaxation parameter and depth of the step from the cell's moments
+// (thread 0 of the group): g = (2 dv)^alpha on the 20-bit grid, mu = rho g,
+// q = exp(-mu dt / eps) (Sec. 3.2, Sec. 4.2); m from the truncation mode.
+__device__ __forceinline__ void cell_params(const InstDev* I, uint32_t cell, uint32_t n, double dmax,
+                                            CellShared& sh)
+{
+    double g = 1.0;
+    if (I->alpha != 0.0) {
+#pragma clang fp contract(off)
+        const double two_dv = 2.0 * sqrt(dmax);
+        g = grid_up20(I->alpha == 1.0 ? two_dv : pow(two_dv, I->alpha));
+    }
+    const double eps = I->eps_cells[cell];
+    double xarg;
+    {
+#pragma clang fp contract(off)
+        const double rho = (double)n * I->rho_factor;
+        const double mu = rho * g;
+        xarg = mu * I->dt / eps;
+    }
+    sh.g = g;
+    double q = exp_neg(xarg);
+    if (!(q >= 0.0 && q <= 1.0)) q = 1.0;  // non-finite velocities: leave the cell unchanged
+    sh.q = q;
+    uint32_t m;
+    if (I->trunc == TRUNC_FIXED) m = I->m_init;
+    else if (I->trunc == TRUNC_ADAPTIVE) m = I->m_state[cell];
+    else m = I->m_cap;
+    if (m < 1) m = 1;
+    if (m > I->m_cap) m = I->m_cap;
+    sh.m = m;
+    sh.attempts = 0;
+    sh.work = 0;
+    sh.overflow = 0;
+}
+
+// a. Split into collision sets (Alg. 4.2) at depth sh.m: wave 0 of the group
+//    draws 64 levels at a time; every lane runs the (uniform) Iround chain.
+template <int G>
+__device__ __forceinline__ void split_levels(const Key& key, uint32_t n, double q, const Levels& L, CellShared& sh,
+                                             uint32_t tid)
+{
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    if (wave == 0) {
+        const uint32_t m = sh.m;
+        uint32_t cbase = 0;
+        uint4 w = draw(key, lane, TAG_SPLIT, 0);
+        double u = u53(w.x, w.y);
+        const uint32_t N0 = iround_prod(q, n, __shfl(u, 0));
+        uint32_t rem = n - N0, k = 0;
+        if (lane == 0) L.N[0] = N0;
+        while (rem > 0 && k < m) {
+            ++k;
+            if (k - cbase >= 64u) {
+                cbase += 64u;
+                w = draw(key, cbase + lane, TAG_SPLIT, 0);
+                u = u53(w.x, w.y);
+            }
+            const uint32_t Nk = iround_prod(q, rem, __shfl(u, (int)(k - cbase)));
+            if (lane == 0) L.N[k] = Nk;
+            rem -= Nk;
+        }
+        if (lane == 0) {
+            L.N[k + 1] = rem;
+            sh.me = k;
+            sh.split_rem = rem;
+            sh.N0 = N0;
+            sh.folds = 0;
+            sh.attempts += 1;
+        }
+    }
+    gsync<G>();
+}
+
+// b. Collision trees, deepest level first (Alg. 4.3 in level order).  Level l
+//    with R_l requests runs ceil(R_l/2) + ceil(max(0, N_l - (R_l mod 2))/2)
+//    collisions; collision c chooses j uniform in {0..l-1} and asks level j (A)
+//    then level l-1-j (B); requests take stable ranks (collision order, A before
+//    B), request r of level t receiving output r of level t.  While the leaves
+//    R_0 exceed n, the deepest level is folded into the remainder.  Returns the
+//    number of collisions (uniform over the group); sets sh.R0, sh.me, sh.folds
+//    and sh.overflow (capacity).
+template <int G>
+__device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32_t n, uint64_t cap,
+                                                          const Levels& L, GroupLds<G>& gl, CellShared& sh,
+                                                          uint32_t* jarr, uint32_t* rA, uint32_t* rB, uint32_t tid)
+{
+    constexpr int NWG = G / 64;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64u - lane));
+    unsigned long long ncoll = 0;
+    for (;;) {
+        const uint32_t me = sh.me;
+        for (uint32_t l = tid; l <= me; l += G) L.run[l] = 0;
+        gsync<G>();
+        ncoll = 0;
+        bool ovf = false;
+        for (uint32_t l = me; l >= 1; --l) {
+            const uint32_t Rl = L.run[l];
+            const uint32_t odd = Rl & 1u, Nl = L.N[l];
+            const uint32_t own = Nl > odd ? (Nl - odd + 1u) / 2u : 0u;
+            const uint32_t Cl = (Rl + 1u) / 2u + own;
+            if (tid == 0) {
+                L.C[l] = Cl;
+                L.Rtot[l] = Rl;
+            }
+            if (Cl == 0) continue;
+            if (ncoll + Cl > cap) {
+                ovf = true;
+                break;
+            }
+            const uint32_t fst = (uint32_t)ncoll;
+            if (l <= 64u) {
+                for (uint32_t b0 = 0; b0 < Cl; b0 += G) {
+                    // sub-level choices: one Philox block per 4 collisions
+                    if (tid < G / 4u && b0 + 4u * tid < Cl) {
+                        const uint4 wv = draw(key, (b0 >> 2) + tid, TAG_TREE, l);
+                        gl.jbuf[4 * tid + 0] = (uint16_t)__umulhi(wv.x, l);
+                        gl.jbuf[4 * tid + 1] = (uint16_t)__umulhi(wv.y, l);
+                        gl.jbuf[4 * tid + 2] = (uint16_t)__umulhi(wv.z, l);
+                        gl.jbuf[4 * tid + 3] = (uint16_t)__umulhi(wv.w, l);
+                    }
+                    gsync<G>();
+                    const uint32_t c = b0 + tid;
+                    const bool valid = c < Cl;
+                    const uint32_t j = valid ? (uint32_t)gl.jbuf[tid] : 0u;
+                    const uint32_t h = l - 1u - j;
+                    unsigned long long myM = 0ull;  // lane b: lanes of this wave whose A goes to level b
+                    const uint32_t nvalid = (Cl - b0 < G ? Cl - b0 : (uint32_t)G);
+                    if (nvalid >= 8u * l || l <= 8u) {
+                        for (uint32_t b = 0; b < l; ++b) {
+                            const unsigned long long M = __ballot(valid && j == b);
+                            myM = (lane == b) ? M : myM;
+                        }
+                    } else {
+                        // few collisions: iterate over the distinct levels present
+                        bool pend = valid;
+                        for (;;) {
+                            const unsigned long long pm = __ballot(pend);
+                            if (pm == 0ull) break;
+                            const uint32_t t = (uint32_t)__shfl((int)j, __ffsll((long long)pm) - 1);
+                            const unsigned long long M = __ballot(valid && j == t);
+                            myM = (lane == t) ? M : myM;
+                            pend = pend && j != t;
+                        }
+                    }
+                    const unsigned long long Mj = shfl64(myM, (int)j), Mh = shfl64(myM, (int)h);
+                    const unsigned long long Mrev = shfl64(myM, (int)(lane < l ? l - 1u - lane : 0u));
+                    const uint32_t local = (uint32_t)(__popcll(Mj & lt) + __popcll(Mh & lt));
+                    if (lane < l) gl.wcnt[wave][lane] = (uint32_t)(__popcll(myM) + __popcll(Mrev));
+                    gsync<G>();
+                    if (tid < l) {
+                        uint32_t acc = L.run[tid];
+#pragma unroll
+                        for (int w = 0; w < NWG; ++w) {
+                            gl.wpre[w][tid] = acc;
+                            acc += gl.wcnt[w][tid];
+                        }
+                        L.run[tid] = acc;
+                    }
+                    gsync<G>();
+                    if (valid) {
+                        jarr[fst + c] = j;
+                        rA[fst + c] = gl.wpre[wave][j] + local;
+                        rB[fst + c] = gl.wpre[wave][h] + local + (j == h ? 1u : 0u);
+                    }
+                    gsync<G>();
+                }
+            } else {
+                // deep levels (natural depth): one wave, distinct target levels by ballot
+                if (wave == 0) {
+                    for (uint32_t b0 = 0; b0 < Cl; b0 += 64u) {
+                        const uint32_t c = b0 + lane;
+                        const bool valid = c < Cl;
+                        const uint32_t j = valid ? tree_choice(key, l, c) : 0u;
+                        const uint32_t ta = j, tb = l - 1u - j;
+                        bool pa = valid, pb = valid;
+                        uint32_t rkA = 0, rkB = 0;
+                        for (;;) {
+                            const unsigned long long mA = __ballot(pa), mB = __ballot(pb);
+                            if (mA == 0ull && mB == 0ull) break;
+                            const uint32_t t = mA ? (uint32_t)__shfl((int)ta, __ffsll((long long)mA) - 1)
+                                                  : (uint32_t)__shfl((int)tb, __ffsll((long long)mB) - 1);
+                            const bool hitA = pa && ta == t, hitB = pb && tb == t;
+                            const unsigned long long eA = __ballot(hitA), eB = __ballot(hitB);
+                            const uint32_t bcnt = __builtin_amdgcn_readfirstlane(L.run[t]);
+                            const uint32_t before = (uint32_t)(__popcll(eA & lt) + __popcll(eB & lt));
+                            if (hitA) {
+                                rkA = bcnt + before;
+                                pa = false;
+                            }
+                            if (hitB) {
+                                rkB = bcnt + before + (ta == t ? 1u : 0u);
+                                pb = false;
+                            }
+                            __builtin_amdgcn_wave_barrier();
+                            if (lane == 0) L.run[t] = bcnt + (uint32_t)(__popcll(eA) + __popcll(eB));
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        }
+                        if (valid) {
+                            jarr[fst + c] = j;
+                            rA[fst + c] = rkA;
+                            rB[fst + c] = rkB;
+                        }
+                    }
+                }
+                gsync<G>();
+            }
+            ncoll += Cl;
+        }
+        if (ovf) {
+            if (tid == 0) sh.overflow = 1u;
+            gsync<G>();
+            return ncoll;
+        }
+        if (tid == 0) sh.R0 = L.run[0];
+        gsync<G>();
+        if (sh.R0 <= n) break;
+        if (tid == 0) {
+            L.N[me] += L.N[me + 1];
+            sh.me = me - 1u;
+            sh.folds += 1;
+        }
+        gsync<G>();
+    }
+    return ncoll;
+}
+
+// Offsets of the outputs taken by requests, role thresholds, capacity
+// (thread 0; the group synchronises).  Returns false on overflow.
+template <int G>
+__device__ __forceinline__ bool level_offsets(uint32_t n, unsigned long long ncoll, uint64_t ocap,
+                                              const Levels& L, CellShared& sh, uint32_t tid)
+{
+    if (tid == 0) {
+        const uint32_t me = sh.me, R0 = sh.R0;
+        unsigned long long no = 0;
+        for (uint32_t l = 1; l <= me; ++l) {
+            L.outoff[l] = (uint32_t)no;
+            no += L.Rtot[l];
+        }
+        sh.ncoll = ncoll;
+        sh.work += ncoll;
+        if (no > ocap) sh.overflow = 1u;
+        const uint32_t N0 = sh.N0, P = n - N0;
+        sh.borrowed = R0 > P ? R0 - P : 0u;
+        sh.n_th = R0 < P ? P - R0 : 0u;
+    }
+    gsync<G>();
+    return sh.overflow == 0u;
+}
+
+// Leaves and sums of the unchanged and thermalized sets over slots
+// [s_begin, s_end) of a cell with NT threads (this thread's share): sums =
+// {kept (vx-m)^2, thermalized (vx-m)^2, thermalized v-m (3), thermalized |v-m|^2}.
+template <typename T, int NT>
+__device__ __forceinline__ void gather_range(const T* vx, const T* vy, const T* vz, const uint32_t* role, T* leaf,
+                                             uint32_t n, uint32_t s_begin, uint32_t s_end, uint32_t N0,
+                                             uint32_t kept_end, uint32_t leaf_end, double mx, double my, double mz,
+                                             uint32_t tid, double (&sums)[6])
+{
+    constexpr int U = 4;
+    const uint32_t P = n - N0;
+    for (uint32_t s0 = s_begin + tid; s0 < s_end; s0 += NT * U) {
+        uint32_t ro[U];
+        T ax[U], ay[U], az[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = s0 + u * NT;
+            const bool ok = i < s_end;
+            ro[u] = ok ? role[i] : 0xFFFFFFFFu;
+            ax[u] = ok ? vx[i] : T(0);
+            ay[u] = ok ? vy[i] : T(0);
+            az[u] = ok ? vz[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = ro[u];
+            if (i == 0xFFFFFFFFu) continue;
+            if (i < kept_end) {
+                const double d = (double)ax[u] - mx;
+                sums[0] += d * d;
+            } else if (i < leaf_end) {
+                const uint32_t r = (i < N0) ? P + (N0 - 1u - i) : i - N0;
+                leaf[r] = ax[u];
+                leaf[n + r] = ay[u];
+                leaf[2 * n + r] = az[u];
+            } else {
+                const double dx = (double)ax[u] - mx, dy = (double)ay[u] - my, dz = (double)az[u] - mz;
+                sums[1] += dx * dx;
+                sums[2] += dx;
+                sums[3] += dy;
+                sums[4] += dz;
+                sums[5] += dx * dx + dy * dy + dz * dz;
+            }
+        }
+    }
+}
+
+// d. Collisions, shallowest level first; all collisions of a level in parallel
+//    (eq. Maxwell_coll-r, eq. n3d-r; Alg. 4.4 acceptance).  Final r goes to the
+//    slot of leaf r.  Per-thread counters and the finals' sum of (vx-m)^2.
+template <typename T, int G>
+__device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const Levels& L, const CellShared& sh,
+                                          const CellMem<T>& M, unsigned long long ncoll, T alpha, T gT, double mx,
+                                          uint32_t tid, uint32_t& dummies, uint32_t& viol, double& sfin)
+{
+    const uint4 pk = draw(key, 0, TAG_PERM, 0);
+    const uint32_t half = perm_half(n);
+    const uint32_t N0 = sh.N0, P = n - N0, me = sh.me;
+    const uint64_t ocap = M.ocap;
+    unsigned long long above = ncoll;  // collisions of deeper levels precede level l's
+    uint32_t fp = 0;                   // finals of shallower levels
+    for (uint32_t l = 1; l <= me; ++l) {
+        const uint32_t Cl = L.C[l], Rl = L.Rtot[l];
+        if (Cl == 0) continue;
+        above -= Cl;
+        const uint32_t fst = (uint32_t)above;
+        const uint32_t oo = L.outoff[l];
+        for (uint32_t c = tid; c < Cl; c += G) {
+            const uint32_t id = fst + c;
+            const uint32_t j = M.jarr[id], h = l - 1u - j;
+            const uint32_t ra = M.rA[id], rb = M.rB[id];
+            Vec3<T> a, b;
+            if (j == 0) {
+                a = Vec3<T>{M.leaf[ra], M.leaf[n + ra], M.leaf[2 * n + ra]};
+            } else {
+                const uint64_t p = (uint64_t)L.outoff[j] + ra;
+                a = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
+            }
+            if (h == 0) {
+                b = Vec3<T>{M.leaf[rb], M.leaf[n + rb], M.leaf[2 * n + rb]};
+            } else {
+                const uint64_t p = (uint64_t)L.outoff[h] + rb;
+                b = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
+            }
+            T xi1, xi2, xacc;
+            Draws<T>::coll(key, l, c, xi1, xi2, xacc);
+            Vec3<T> out[2];
+            if (!collide<T>(a, b, xi1, xi2, xacc, alpha, gT, out[0], out[1], viol)) dummies++;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t o = 2u * c + (uint32_t)k;
+                if (o < Rl) {
+                    const uint64_t p = (uint64_t)oo + o;
+                    M.outv[p] = out[k].x;
+                    M.outv[ocap + p] = out[k].y;
+                    M.outv[2 * ocap + p] = out[k].z;
+                } else {
+                    const uint32_t r = fp + (o - Rl);
+                    const uint32_t fs = perm_forward(r < P ? N0 + r : N0 - 1u - (r - P), n, half, pk);
+                    M.fin[fs] = out[k].x;
+                    M.fin[n + fs] = out[k].y;
+                    M.fin[2 * n + fs] = out[k].z;
+                    const double d = (double)out[k].x - mx;
+                    sfin += d * d;
+                }
+            }
+        }
+        fp += 2u * Cl - Rl;
+        gsync<G>();
+    }
+}
+
+// e. Adaptive test of Sec. 4.3 (thread 0): S^{n+1,m} from the unchanged set, the
+//    finals and the analytic Maxwellian part; halve / keep / redo at 2m.  Also
+//    records the removed set's mean and energy.  all = {kept (vx-m)^2, th
+//    (vx-m)^2, th v-m (3), th |v-m|^2, finals (vx-m)^2}.
+__device__ __forceinline__ void decide(InstDev* I, uint32_t cell, uint32_t n, const double (&all)[7], double mx,
+                                       double my, double mz, CellShared& sh)
+{
+    double Snew = all[0] + all[6];
+    const uint32_t n_th = sh.n_th;
+    if (n_th >= 2) {
+        const double nt = (double)n_th;
+        const double d0 = all[2] / nt, d1 = all[3] / nt, d2 = all[4] / nt;
+        sh.ur[0] = mx + d0;
+        sh.ur[1] = my + d1;
+        sh.ur[2] = mz + d2;
+        const double E = all[5] - nt * (d0 * d0 + d1 * d1 + d2 * d2);
+        sh.a_th = E > 0.0 ? E : 0.0;  // energy of the removed set
+        Snew += E / 3.0 + nt * d0 * d0;
+    } else {
+        Snew += all[1];
+        sh.a_th = 0.0;
+    }
+    uint32_t decision = 1;  // accept
+    sh.E1 = 0.0;
+    if (I->trunc == TRUNC_ADAPTIVE) {
+        const uint32_t m = sh.m;
+        if (sh.Sn == 0.0) {
+            I->m_state[cell] = m;
+        } else {
+#pragma clang fp contract(off)
+            Snew /= (double)n;
+            const double E1 = fabs(Snew - sh.Sn) / fabs(sh.Sn);
+            sh.E1 = E1;
+            if (E1 < I->delta1) I->m_state[cell] = (m / 2u > 1u) ? m / 2u : 1u;
+            else if (E1 <= I->delta2) I->m_state[cell] = m;
+            else if (m >= I->m_cap || sh.split_rem == 0u) I->m_state[cell] = m;
+            else {
+                sh.m = (2u * m < I->m_cap) ? 2u * m : I->m_cap;
+                decision = 0;
+            }
+        }
+    }
+    sh.decision = decision;
+}
+
+__device__ __forceinline__ void write_stats(CellStats* st, uint32_t n, const CellShared& sh)
+{
+    CellStats s{};
+    s.n = n;
+    s.N0 = sh.N0;
+    s.m_eff = sh.me;
+    s.m_used = sh.m;
+    s.attempts = sh.attempts;
+    s.R0 = sh.R0;
+    s.n_th = sh.n_th;
+    s.borrowed = sh.borrowed;
+    s.folds = sh.folds;
+    s.status = 0;
+    s.collisions = sh.ncoll;
+    s.dummies = sh.dummies;
+    s.violations = sh.viol;
+    s.work_collisions = sh.work;
+    s.q = sh.q;
+    s.g = sh.g;
+    s.E1 = sh.E1;
+    *st = s;
+}
+
+}  // namespace trmc

@@ -1,0 +1,468 @@
+// k_tiled.hip -- the collision step of large homogeneous cells as a pipeline of
+// lean streaming kernels over fixed tiles of kTile slots (high occupancy, many
+// loads in flight) around per-cell kernels for the parts that need the whole
+// cell (the trees and the collisions):
+//
+//   k_tile_prep    tiles: role of every slot (keyed permutation), partial sums
+//   k_tile_dv      tiles: max |v - mean|^2 for the VHS majorant
+//   k_big_tree     cells: moments, tau, split (Alg. 4.2), trees (Alg. 4.3)
+//   k_tile_gather  tiles: leaves, partial sums of the unchanged / thermalized sets
+//   k_big_collide  cells: collisions level by level, adaptive test (Sec. 4.3);
+//                  a rejected attempt is redone inside, tile by tile, with the
+//                  same tile sums as k_tile_gather
+//   k_tile_zsum    tiles: sums of the Maxwellian normals of the thermalized set
+//   k_tile_write   tiles: leaves take the finals, thermalized slots the rescaled
+//                  Maxwellian samples (normals drawn again from their keys)
+//
+// Partial sums are combined in tile order, so the result does not depend on
+// scheduling.  Same arithmetic as the whole-cell kernel; only the order of the
+// FP64 reductions differs (fixed per cell by its size).
+#include <hip/hip_runtime.h>
+
+#include "collide_core.h"
+
+namespace trmc {
+
+constexpr int kTT = 512;  // threads of every tiled kernel
+
+// State of a large cell kept between the kernels of one step.
+struct BigState {
+    CellShared sh;
+    unsigned long long ncoll;
+    uint32_t pad[2];
+};
+
+static_assert(sizeof(BigState) <= kBigStateBytes, "BigState exceeds its reserved bytes");
+
+__device__ __forceinline__ BigState* big_state(const InstDev* I) { return reinterpret_cast<BigState*>(I->bigstate); }
+__device__ __forceinline__ uint32_t* big_levels(const InstDev* I)
+{
+    return reinterpret_cast<uint32_t*>(I->bigstate + kBigStateBytes);
+}
+
+// Tile -> (large cell, tile index within the cell) by binary search of the prefix.
+__device__ __forceinline__ void tile_of(const uint32_t* prefix, uint32_t nb, uint32_t t, uint32_t& b, uint32_t& k)
+{
+    uint32_t lo = 0, hi = nb;  // prefix[lo] <= t < prefix[hi]
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    b = lo;
+    k = t - prefix[lo];
+}
+
+template <typename T>
+struct CellView {
+    InstDev* I;
+    uint32_t n;
+    T *vx, *vy, *vz;
+    __device__ __forceinline__ CellView(InstDev* inst)
+    {
+        I = inst;
+        n = I->cell_off[1] - I->cell_off[0];
+        vx = reinterpret_cast<T*>(I->vx[0]);
+        vy = reinterpret_cast<T*>(I->vy[0]);
+        vz = reinterpret_cast<T*>(I->vz[0]);
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ bigs, const uint32_t* __restrict__ prefix,
+                                                   uint32_t nb)
+{
+    __shared__ double t_red[(kTT / 64) * 8];
+    uint32_t b, k;
+    tile_of(prefix, nb, blockIdx.x, b, k);
+    CellView<T> V(bigs[b].inst);
+    const uint32_t n = V.n;
+    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
+    const Key key{V.I->seed, V.I->uid, 0u, V.I->step};
+    const uint4 pk = draw(key, 0, TAG_PERM, 0);
+    const uint32_t half = perm_half(n);
+    uint32_t* role = reinterpret_cast<uint32_t*>(V.I->scratch);
+    const double c0 = (double)V.vx[0];
+    constexpr int U = 4;
+    double s[4] = {0, 0, 0, 0};
+    T ax[U], ay[U], az[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t i = s_begin + threadIdx.x + u * kTT;
+        const bool ok = i < s_end;
+        ax[u] = ok ? V.vx[i] : T(0);
+        ay[u] = ok ? V.vy[i] : T(0);
+        az[u] = ok ? V.vz[i] : T(0);
+    }
+    for (uint32_t s0 = s_begin + threadIdx.x; s0 < s_end; s0 += kTT * U) {
+        T bx[U], by[U], bz[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = s0 + kTT * U + u * kTT;
+            const bool ok = i < s_end;
+            bx[u] = ok ? V.vx[i] : T(0);
+            by[u] = ok ? V.vy[i] : T(0);
+            bz[u] = ok ? V.vz[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = s0 + u * kTT;
+            if (i < s_end) {
+                const double dx = (double)ax[u] - c0;
+                s[0] += dx;
+                s[1] += (double)ay[u];
+                s[2] += (double)az[u];
+                s[3] += dx * dx;
+                role[i] = perm_inverse(i, n, half, pk);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ax[u] = bx[u];
+            ay[u] = by[u];
+            az[u] = bz[u];
+        }
+    }
+    gsum<kTT, 4>(s, t_red);
+    if (threadIdx.x == 0) {
+        double* tp = V.I->tpart + 8ull * k;
+        tp[0] = s[0];
+        tp[1] = s[1];
+        tp[2] = s[2];
+        tp[3] = s[3];
+    }
+}
+
+// Cell mean from the prep partials (tile order; identical wherever computed).
+__device__ __forceinline__ void cell_mean(const InstDev* I, uint32_t n, double c0, double& mx, double& my, double& mz,
+                                          double& Sn)
+{
+    const uint32_t nt = (n + kTile - 1) / kTile;
+    double a = 0, b = 0, c = 0, d = 0;
+    for (uint32_t t = 0; t < nt; ++t) {
+        const double* tp = I->tpart + 8ull * t;
+        a += tp[0];
+        b += tp[1];
+        c += tp[2];
+        d += tp[3];
+    }
+    const double inv = 1.0 / (double)n;
+    const double dxm = a * inv;
+    mx = c0 + dxm;
+    my = b * inv;
+    mz = c * inv;
+    const double sn = d * inv - dxm * dxm;
+    Sn = sn > 0.0 ? sn : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_tile_dv(const CellRef* __restrict__ bigs, const uint32_t* __restrict__ prefix,
+                                                 uint32_t nb)
+{
+    __shared__ double t_red[(kTT / 64) * 8];
+    uint32_t b, k;
+    tile_of(prefix, nb, blockIdx.x, b, k);
+    CellView<T> V(bigs[b].inst);
+    if (V.I->alpha == 0.0) return;
+    const uint32_t n = V.n;
+    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
+    __shared__ double mean[3];
+    if (threadIdx.x == 0) {
+        double Sn;
+        cell_mean(V.I, n, (double)V.vx[0], mean[0], mean[1], mean[2], Sn);
+    }
+    __syncthreads();
+    const double mx = mean[0], my = mean[1], mz = mean[2];
+    constexpr int U = 4;
+    double d2max = 0.0;
+    for (uint32_t s0 = s_begin + threadIdx.x; s0 < s_end; s0 += kTT * U) {
+        T ax[U], ay[U], az[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = s0 + u * kTT;
+            const bool ok = i < s_end;
+            ax[u] = ok ? V.vx[i] : T(0);
+            ay[u] = ok ? V.vy[i] : T(0);
+            az[u] = ok ? V.vz[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (s0 + u * kTT < s_end) {
+                const double dx = (double)ax[u] - mx, dy = (double)ay[u] - my, dz = (double)az[u] - mz;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                d2max = d2 > d2max ? d2 : d2max;
+            }
+        }
+    }
+    d2max = gmax<kTT>(d2max, t_red);
+    if (threadIdx.x == 0) V.I->tpart[8ull * k + 4] = d2max;
+}
+
+// Per-cell kernels: one workgroup of kTT threads per large cell.
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_big_tree(const CellRef* __restrict__ bigs, uint32_t nb, uint32_t lv_stride)
+{
+    extern __shared__ uint32_t lds_levels[];
+    __shared__ GroupLds<kTT> gl;
+    if (blockIdx.x >= nb) return;
+    InstDev* I = bigs[blockIdx.x].inst;
+    const uint32_t n = I->cell_off[1] - I->cell_off[0];
+    CellShared& sh = gl.sh;
+    const uint32_t tid = threadIdx.x;
+    const Key key{I->seed, I->uid, 0u, I->step};
+    CellMem<T> M;
+    M.init(I, 0, 0, n);
+    Levels L = levels_at(lds_levels, lv_stride);
+    if (tid == 0) {
+        const T* vx = reinterpret_cast<const T*>(I->vx[0]);
+        cell_mean(I, n, (double)vx[0], sh.mean[0], sh.mean[1], sh.mean[2], sh.Sn);
+        double dmax = 0.0;
+        if (I->alpha != 0.0) {
+            const uint32_t nt = (n + kTile - 1) / kTile;
+            for (uint32_t t = 0; t < nt; ++t) dmax = fmax(dmax, I->tpart[8ull * t + 4]);
+        }
+        cell_params(I, 0, n, dmax, sh);
+    }
+    gsync<kTT>();
+    split_levels<kTT>(key, n, sh.q, L, sh, tid);
+    const unsigned long long ncoll = build_trees<kTT>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
+    if (!sh.overflow) level_offsets<kTT>(n, ncoll, M.ocap, L, sh, tid);
+    // keep the state and the level arrays for the next kernels
+    BigState* S = big_state(I);
+    uint32_t* gL = big_levels(I);
+    for (uint32_t i = tid; i < 5u * lv_stride; i += kTT) gL[i] = lds_levels[i];
+    if (tid == 0) {
+        S->sh = sh;
+        S->ncoll = ncoll;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_tile_gather(const CellRef* __restrict__ bigs,
+                                                     const uint32_t* __restrict__ prefix, uint32_t nb)
+{
+    __shared__ double t_red[(kTT / 64) * 8];
+    uint32_t b, k;
+    tile_of(prefix, nb, blockIdx.x, b, k);
+    CellView<T> V(bigs[b].inst);
+    const uint32_t n = V.n;
+    const BigState* S = big_state(V.I);
+    if (S->sh.overflow) return;
+    const uint32_t N0 = S->sh.N0, R0 = S->sh.R0, borrowed = S->sh.borrowed, P = n - N0;
+    const uint32_t kept_end = N0 - borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
+    CellMem<T> M;
+    M.init(V.I, 0, 0, n);
+    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
+    double sums[6] = {0, 0, 0, 0, 0, 0};
+    gather_range<T, kTT>(V.vx, V.vy, V.vz, M.role, M.leaf, n, s_begin, s_end, N0, kept_end, leaf_end,
+                         S->sh.mean[0], S->sh.mean[1], S->sh.mean[2], threadIdx.x, sums);
+    gsum<kTT, 6>(sums, t_red);
+    if (threadIdx.x == 0) {
+        double* tp = V.I->tpart + 8ull * k;
+        for (int q = 0; q < 6; ++q) tp[q] = sums[q];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__ bigs, uint32_t nb, uint32_t lv_stride)
+{
+    extern __shared__ uint32_t lds_levels[];
+    __shared__ GroupLds<kTT> gl;
+    __shared__ double tsum[6];
+    if (blockIdx.x >= nb) return;
+    InstDev* I = bigs[blockIdx.x].inst;
+    const uint32_t n = I->cell_off[1] - I->cell_off[0];
+    const uint32_t tid = threadIdx.x;
+    CellShared& sh = gl.sh;
+    BigState* S = big_state(I);
+    uint32_t* gL = big_levels(I);
+    for (uint32_t i = tid; i < 5u * lv_stride; i += kTT) lds_levels[i] = gL[i];
+    if (tid == 0) sh = S->sh;
+    gsync<kTT>();
+    CellStats* st = I->stats;
+    if (sh.overflow) {
+        if (tid == 0) {
+            CellStats s{};
+            s.n = n;
+            s.status = CELL_OVERFLOW;
+            s.m_used = sh.m;
+            *st = s;
+            atomicOr(I->error, CELL_OVERFLOW);
+        }
+        return;
+    }
+    const Key key{I->seed, I->uid, 0u, I->step};
+    const T* vx = reinterpret_cast<const T*>(I->vx[0]);
+    const T* vy = reinterpret_cast<const T*>(I->vy[0]);
+    const T* vz = reinterpret_cast<const T*>(I->vz[0]);
+    CellMem<T> M;
+    M.init(I, 0, 0, n);
+    Levels L = levels_at(lds_levels, lv_stride);
+    const double mx = sh.mean[0], my = sh.mean[1], mz = sh.mean[2];
+    const T alpha = (T)I->alpha;
+    const T gT = (T)sh.g;
+    const uint32_t nt = (n + kTile - 1) / kTile;
+    unsigned long long ncoll = S->ncoll;
+    // sums of the first attempt from k_tile_gather, in tile order
+    if (tid == 0) {
+        for (int q = 0; q < 6; ++q) tsum[q] = 0.0;
+        for (uint32_t t = 0; t < nt; ++t)
+            for (int q = 0; q < 6; ++q) tsum[q] += I->tpart[8ull * t + q];
+    }
+    gsync<kTT>();
+    for (;;) {
+        uint32_t dummies = 0, viol = 0;
+        double sfin = 0.0;
+        bottom_up<T, kTT>(key, n, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
+        double fs[1] = {sfin};
+        gsum<kTT, 1>(fs, gl.red);
+        const uint32_t td = gsum_u32<kTT>(dummies, gl.redu);
+        const uint32_t tv = gsum_u32<kTT>(viol, gl.redu);
+        if (tid == 0) {
+            const double all[7] = {tsum[0], tsum[1], tsum[2], tsum[3], tsum[4], tsum[5], fs[0]};
+            sh.dummies = td;
+            sh.viol = tv;
+            decide(I, 0, n, all, mx, my, mz, sh);
+        }
+        gsync<kTT>();
+        if (sh.decision) break;
+        // redo at depth sh.m: trees, then the tile sums exactly as k_tile_gather forms them
+        split_levels<kTT>(key, n, sh.q, L, sh, tid);
+        ncoll = build_trees<kTT>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
+        if (sh.overflow || !level_offsets<kTT>(n, ncoll, M.ocap, L, sh, tid)) break;
+        const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
+        const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
+        if (tid == 0)
+            for (int q = 0; q < 6; ++q) tsum[q] = 0.0;
+        for (uint32_t t = 0; t < nt; ++t) {
+            const uint32_t s_begin = t * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
+            double sums[6] = {0, 0, 0, 0, 0, 0};
+            gather_range<T, kTT>(vx, vy, vz, M.role, M.leaf, n, s_begin, s_end, N0, kept_end, leaf_end, mx, my, mz,
+                                 tid, sums);
+            gsum<kTT, 6>(sums, gl.red);
+            if (tid == 0)
+                for (int q = 0; q < 6; ++q) tsum[q] += sums[q];
+        }
+        gsync<kTT>();
+    }
+    if (tid == 0) {
+        if (sh.overflow) {
+            CellStats s{};
+            s.n = n;
+            s.status = CELL_OVERFLOW;
+            s.m_used = sh.m;
+            *st = s;
+            atomicOr(I->error, CELL_OVERFLOW);
+        } else {
+            write_stats(st, n, sh);
+        }
+        S->sh = sh;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_tile_zsum(const CellRef* __restrict__ bigs,
+                                                   const uint32_t* __restrict__ prefix, uint32_t nb)
+{
+    __shared__ double t_red[(kTT / 64) * 8];
+    uint32_t b, k;
+    tile_of(prefix, nb, blockIdx.x, b, k);
+    InstDev* I = bigs[b].inst;
+    const BigState* S = big_state(I);
+    const uint32_t n_th = S->sh.n_th;
+    if (S->sh.overflow || n_th < 2) return;
+    const uint32_t t_begin = k * kTile, t_end = (t_begin + kTile < n_th) ? t_begin + kTile : n_th;
+    const Key key{I->seed, I->uid, 0u, I->step};
+    double zs[4] = {0, 0, 0, 0};
+    for (uint32_t t = t_begin + threadIdx.x; t < t_end; t += kTT) {
+        const Vec3<T> z = Draws<T>::normals(key, t);
+        const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
+        zs[0] += zx;
+        zs[1] += zy;
+        zs[2] += zz;
+        zs[3] += zx * zx + zy * zy + zz * zz;
+    }
+    gsum<kTT, 4>(zs, t_red);
+    if (threadIdx.x == 0) {
+        double* tp = I->tpart + 8ull * k;
+        for (int q = 0; q < 4; ++q) tp[q] = zs[q];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ bigs,
+                                                    const uint32_t* __restrict__ prefix, uint32_t nb)
+{
+    uint32_t b, k;
+    tile_of(prefix, nb, blockIdx.x, b, k);
+    CellView<T> V(bigs[b].inst);
+    const uint32_t n = V.n;
+    const BigState* S = big_state(V.I);
+    if (S->sh.overflow) return;
+    const uint32_t N0 = S->sh.N0, R0 = S->sh.R0, P = n - N0, n_th = S->sh.n_th;
+    const uint32_t kept_end = N0 - S->sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
+    __shared__ double par[7];  // a, zbar (3), ur (3)
+    if (threadIdx.x == 0 && n_th >= 2) {
+        const uint32_t ntz = (n_th + kTile - 1) / kTile;
+        double z[4] = {0, 0, 0, 0};
+        for (uint32_t t = 0; t < ntz; ++t)
+            for (int q = 0; q < 4; ++q) z[q] += V.I->tpart[8ull * t + q];
+        const double nt = (double)n_th;
+        const double zb0 = z[0] / nt, zb1 = z[1] / nt, zb2 = z[2] / nt;
+        const double Z = z[3] - nt * (zb0 * zb0 + zb1 * zb1 + zb2 * zb2);
+        par[0] = Z > 0.0 ? sqrt(S->sh.a_th / Z) : 0.0;
+        par[1] = zb0;
+        par[2] = zb1;
+        par[3] = zb2;
+        par[4] = S->sh.ur[0];
+        par[5] = S->sh.ur[1];
+        par[6] = S->sh.ur[2];
+    }
+    __syncthreads();
+    const bool thermalize = n_th >= 2;
+    const double a = thermalize ? par[0] : 0.0;
+    const double z0 = thermalize ? par[1] : 0.0, z1 = thermalize ? par[2] : 0.0, z2 = thermalize ? par[3] : 0.0;
+    const double u0 = thermalize ? par[4] : 0.0, u1 = thermalize ? par[5] : 0.0, u2 = thermalize ? par[6] : 0.0;
+    const Key key{V.I->seed, V.I->uid, 0u, V.I->step};
+    CellMem<T> M;
+    M.init(V.I, 0, 0, n);
+    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
+    constexpr int U = 4;
+    for (uint32_t s0 = s_begin + threadIdx.x; s0 < s_end; s0 += kTT * U) {
+        uint32_t ro[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = s0 + u * kTT;
+            ro[u] = i < s_end ? M.role[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t s = s0 + u * kTT;
+            const uint32_t i = ro[u];
+            if (s >= s_end || i < kept_end) continue;
+            if (i < leaf_end) {
+                V.vx[s] = M.fin[s];
+                V.vy[s] = M.fin[n + s];
+                V.vz[s] = M.fin[2 * n + s];
+            } else if (thermalize) {
+                const Vec3<T> z = Draws<T>::normals(key, i - leaf_end);
+                V.vx[s] = (T)(u0 + a * ((double)z.x - z0));
+                V.vy[s] = (T)(u1 + a * ((double)z.y - z1));
+                V.vz[s] = (T)(u2 + a * ((double)z.z - z2));
+            }
+        }
+    }
+}
+
+#define TRMC_TILED_INSTANTIATE(T)                                                              \
+    template __global__ void k_tile_prep<T>(const CellRef*, const uint32_t*, uint32_t);        \
+    template __global__ void k_tile_dv<T>(const CellRef*, const uint32_t*, uint32_t);          \
+    template __global__ void k_big_tree<T>(const CellRef*, uint32_t, uint32_t);                \
+    template __global__ void k_tile_gather<T>(const CellRef*, const uint32_t*, uint32_t);      \
+    template __global__ void k_big_collide<T>(const CellRef*, uint32_t, uint32_t);             \
+    template __global__ void k_tile_zsum<T>(const CellRef*, const uint32_t*, uint32_t);        \
+    template __global__ void k_tile_write<T>(const CellRef*, const uint32_t*, uint32_t);
+TRMC_TILED_INSTANTIATE(float)
+TRMC_TILED_INSTANTIATE(double)
+
+}  // namespace trmc

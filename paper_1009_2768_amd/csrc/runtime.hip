@@ -15,7 +15,7 @@
 
 namespace trmc {
 template <typename T>
-__global__ void k_collide(const CellRef*, uint32_t, uint32_t);
+__global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
 template <typename T>
 __global__ void k_hist(InstDev*);
 __global__ void k_scan_tiles(InstDev*);
@@ -24,6 +24,20 @@ template <typename T>
 __global__ void k_scatter(InstDev*);
 template <typename T>
 __global__ void k_moments(const CellRef*, uint32_t);
+template <typename T>
+__global__ void k_tile_prep(const CellRef*, const uint32_t*, uint32_t);
+template <typename T>
+__global__ void k_tile_dv(const CellRef*, const uint32_t*, uint32_t);
+template <typename T>
+__global__ void k_big_tree(const CellRef*, uint32_t, uint32_t);
+template <typename T>
+__global__ void k_tile_gather(const CellRef*, const uint32_t*, uint32_t);
+template <typename T>
+__global__ void k_big_collide(const CellRef*, uint32_t, uint32_t);
+template <typename T>
+__global__ void k_tile_zsum(const CellRef*, const uint32_t*, uint32_t);
+template <typename T>
+__global__ void k_tile_write(const CellRef*, const uint32_t*, uint32_t);
 __global__ void k_advance(InstDev* const*, uint32_t);
 }  // namespace trmc
 
@@ -42,7 +56,7 @@ uint32_t sort_tile_h(uint32_t n_cells)
 }
 
 struct Layout {
-    size_t inst, refs, eps, off, mstate, stats, mom, hist, bx, bvx, bvy, bvz, scratch, total;
+    size_t inst, refs, eps, off, mstate, stats, mom, hist, bx, bvx, bvy, bvz, tpart, big, scratch, total;
     uint32_t n_tiles;
 };
 
@@ -69,6 +83,10 @@ Layout layout_of(const trmc_desc& d)
         L.bvx = p;   p += al(sz * n);
         L.bvy = p;   p += al(sz * n);
         L.bvz = p;   p += al(sz * n);
+    } else {
+        // tiled pipeline of large homogeneous cells: tile sums, state and level arrays
+        L.tpart = p; p += al(sizeof(double) * 8 * ((n + kTile - 1) / kTile));
+        L.big = p;   p += al(kBigStateBytes + sizeof(uint32_t) * 5 * ((size_t)d.m_cap + 2));
     }
     L.scratch = p;
     p += al(scratch_bpp((uint32_t)sz) * n + scratch_cpc((uint32_t)sz) * nc);
@@ -125,9 +143,13 @@ struct trmc_ctx {
     size_t ws_bytes = 0;
     uint32_t max_inst = 0, max_cells = 0;
     uint32_t* error = nullptr;
-    CellRef* work[2] = {nullptr, nullptr};  // [0] FP32, [1] FP64
-    uint32_t n_work[2] = {0, 0};
-    uint32_t lv_stride[2] = {2, 2};
+    // work lists of the collision step, [precision: 0 FP32, 1 FP64][class]: class 0 =
+    // workgroup per cell, 1 = wave per cell, 2 = tiled pipeline (large homogeneous cells)
+    CellRef* work[2][3] = {};
+    uint32_t n_work[2][3] = {};
+    uint32_t lv_stride[2][3] = {{2, 2, 2}, {2, 2, 2}};
+    uint32_t* tile_prefix[2] = {nullptr, nullptr};  // [n_work[k][2] + 1] first tile of each tiled cell
+    uint32_t n_tiles[2] = {0, 0};
     InstDev** inst_ptrs = nullptr;
     uint32_t n_active = 0;
     uint32_t cells_used = 0;
@@ -139,42 +161,62 @@ namespace {
 
 size_t ctx_bytes(uint32_t max_inst, uint32_t max_cells)
 {
-    return al(sizeof(uint32_t)) + 2 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
-           al(sizeof(InstDev*) * std::max(1u, max_inst));
+    return al(sizeof(uint32_t)) + 6 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
+           2 * al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1)) + al(sizeof(InstDev*) * std::max(1u, max_inst));
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? 0 : TRMC_EIO; }
 
-// Rebuild the device work lists (largest cells first) and the instance list.
+// Rebuild the device work lists and the instance list.  Homogeneous cells of
+// more than kSmallCell particles take the tiled pipeline; cells expected to hold
+// at most kSmallCell particles (with m_cap <= kSmallDepth, which bounds their
+// level arrays in LDS) take one wave each; the others one workgroup each.  Lists
+// are ordered by expected size, largest first.
 int rebuild_tables(trmc_ctx* c)
 {
-    std::vector<CellRef> w[2];
-    std::vector<std::pair<double, CellRef>> order[2];
+    std::vector<std::pair<double, CellRef>> order[2][3];
     std::vector<InstDev*> ptrs;
-    uint32_t stride[2] = {2, 2};
+    uint32_t stride[2][3] = {{2, 2, 2}, {2, 2, 2}};
     for (auto& s : c->slots) {
         if (!s.active) continue;
         ptrs.push_back(s.dev);
         const int k = s.desc.precision == TRMC_FP64 ? 1 : 0;
-        const uint32_t nc = s.desc.geometry == TRMC_SLAB1D ? s.desc.n_cells : 1u;
+        const bool slab = s.desc.geometry == TRMC_SLAB1D;
+        const uint32_t nc = slab ? s.desc.n_cells : 1u;
         const double per = (double)s.desc.n_particles / nc;
-        for (uint32_t cc = 0; cc < nc; ++cc) {
-            CellRef r{s.dev, cc, 0};
-            order[k].push_back({per, r});
-        }
-        stride[k] = std::max(stride[k], s.desc.m_cap + 2u);
+        int cls;
+        if (!slab && per > (double)kSmallCell) cls = 2;
+        else if (per <= (double)kSmallCell && s.desc.m_cap <= kSmallDepth) cls = 1;
+        else cls = 0;
+        for (uint32_t cc = 0; cc < nc; ++cc) order[k][cls].push_back({per, CellRef{s.dev, cc, 0}});
+        stride[k][cls] = std::max(stride[k][cls], s.desc.m_cap + 2u);
     }
+    std::vector<CellRef> w;
+    std::vector<uint32_t> prefix;
     for (int k = 0; k < 2; ++k) {
-        std::stable_sort(order[k].begin(), order[k].end(),
-                         [](const auto& a, const auto& b) { return a.first > b.first; });
-        for (auto& e : order[k]) w[k].push_back(e.second);
-        if (!w[k].empty()) {
-            hipError_t e = hipMemcpyAsync(c->work[k], w[k].data(), sizeof(CellRef) * w[k].size(),
-                                          hipMemcpyHostToDevice, c->stream);
-            if (e != hipSuccess) return TRMC_EIO;
+        for (int cls = 0; cls < 3; ++cls) {
+            auto& o = order[k][cls];
+            std::stable_sort(o.begin(), o.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+            w.clear();
+            for (auto& e : o) w.push_back(e.second);
+            if (!w.empty()) {
+                hipError_t e = hipMemcpyAsync(c->work[k][cls], w.data(), sizeof(CellRef) * w.size(),
+                                              hipMemcpyHostToDevice, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // w is reused
+                if (e != hipSuccess) return TRMC_EIO;
+            }
+            c->n_work[k][cls] = (uint32_t)w.size();
+            c->lv_stride[k][cls] = stride[k][cls];
+            if (cls == 2) {
+                prefix.assign(1, 0u);
+                for (auto& e : o) prefix.push_back(prefix.back() + (uint32_t)((e.first + kTile - 1) / kTile));
+                c->n_tiles[k] = prefix.back();
+                hipError_t e = hipMemcpyAsync(c->tile_prefix[k], prefix.data(), sizeof(uint32_t) * prefix.size(),
+                                              hipMemcpyHostToDevice, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+                if (e != hipSuccess) return TRMC_EIO;
+            }
         }
-        c->n_work[k] = (uint32_t)w[k].size();
-        c->lv_stride[k] = stride[k];
     }
     if (!ptrs.empty()) {
         hipError_t e = hipMemcpyAsync(c->inst_ptrs, ptrs.data(), sizeof(InstDev*) * ptrs.size(),
@@ -262,6 +304,8 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     h.scratch_bpp = scratch_bpp((uint32_t)sz);
     h.scratch_cpc = scratch_cpc((uint32_t)sz);
     h.error = c->error;
+    h.tpart = d->geometry == TRMC_SLAB1D ? nullptr : reinterpret_cast<double*>(ws + L.tpart);
+    h.bigstate = d->geometry == TRMC_SLAB1D ? nullptr : ws + L.big;
 
     std::vector<double> eps(nc);
     std::vector<uint32_t> off(nc + 1, 0), ms(nc);
@@ -310,6 +354,37 @@ int launch_slab(trmc_ctx* c, Slot& s)
     hipLaunchKernelGGL(k_scan_tiles, dim3((nc + 255) / 256), dim3(256), 0, c->stream, s.dev);
     hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, c->stream, s.dev);
     hipLaunchKernelGGL(k_scatter<T>, dim3(nt), dim3(1024), sizeof(uint32_t) * nc, c->stream, s.dev);
+    return hip_status(hipGetLastError());
+}
+
+
+// One collision step of every cell of precision k: the tiled pipeline for large
+// homogeneous cells, then the whole-cell kernel for the rest.
+template <typename T>
+int launch_collide(trmc_ctx* c, int k)
+{
+    const uint32_t nt = c->n_work[k][2];
+    if (nt) {
+        const CellRef* bigs = c->work[k][2];
+        const uint32_t* pre = c->tile_prefix[k];
+        const uint32_t tiles = c->n_tiles[k];
+        const size_t lds = sizeof(uint32_t) * 5 * c->lv_stride[k][2];
+        hipLaunchKernelGGL(k_tile_prep<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+        hipLaunchKernelGGL(k_tile_dv<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+        hipLaunchKernelGGL(k_big_tree<T>, dim3(nt), dim3(512), lds, c->stream, bigs, nt, c->lv_stride[k][2]);
+        hipLaunchKernelGGL(k_tile_gather<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+        hipLaunchKernelGGL(k_big_collide<T>, dim3(nt), dim3(512), lds, c->stream, bigs, nt, c->lv_stride[k][2]);
+        hipLaunchKernelGGL(k_tile_zsum<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+        hipLaunchKernelGGL(k_tile_write<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+    }
+    const uint32_t nb = c->n_work[k][0], ns = c->n_work[k][1];
+    if (nb + ns) {
+        const uint32_t small_blocks = (ns + kSmallPerBlock - 1) / kSmallPerBlock;
+        const size_t lds = std::max(sizeof(uint32_t) * 5 * c->lv_stride[k][0],
+                                    sizeof(uint32_t) * 5 * kSmallPerBlock * c->lv_stride[k][1]);
+        hipLaunchKernelGGL(k_collide<T>, dim3(nb + small_blocks), dim3(kCollideThreads), lds, c->stream,
+                           c->work[k][0], nb, c->lv_stride[k][0], c->work[k][1], ns, c->lv_stride[k][1]);
+    }
     return hip_status(hipGetLastError());
 }
 
@@ -379,10 +454,14 @@ int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trm
     size_t p = 0;
     c->error = reinterpret_cast<uint32_t*>(c->ws + p);
     p += al(sizeof(uint32_t));
-    c->work[0] = reinterpret_cast<CellRef*>(c->ws + p);
-    p += al(sizeof(CellRef) * std::max(1u, max_cells));
-    c->work[1] = reinterpret_cast<CellRef*>(c->ws + p);
-    p += al(sizeof(CellRef) * std::max(1u, max_cells));
+    for (int k = 0; k < 2; ++k) {
+        for (int cls = 0; cls < 3; ++cls) {
+            c->work[k][cls] = reinterpret_cast<CellRef*>(c->ws + p);
+            p += al(sizeof(CellRef) * std::max(1u, max_cells));
+        }
+        c->tile_prefix[k] = reinterpret_cast<uint32_t*>(c->ws + p);
+        p += al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1));
+    }
     c->inst_ptrs = reinterpret_cast<InstDev**>(c->ws + p);
     p += al(sizeof(InstDev*) * std::max(1u, max_instances));
     if (hipMemsetAsync(c->error, 0, sizeof(uint32_t), c->stream) != hipSuccess) {
@@ -434,14 +513,10 @@ int trmc_step(trmc_ctx* c, uint32_t n_steps)
             int rc = s.host.precision == PREC_FP64 ? launch_slab<double>(c, s) : launch_slab<float>(c, s);
             if (rc) return c->sticky = rc;
         }
-        if (c->n_work[0])
-            hipLaunchKernelGGL(k_collide<float>, dim3(c->n_work[0]), dim3(kCollideThreads),
-                               sizeof(uint32_t) * 7 * c->lv_stride[0], c->stream, c->work[0], c->n_work[0],
-                               c->lv_stride[0]);
-        if (c->n_work[1])
-            hipLaunchKernelGGL(k_collide<double>, dim3(c->n_work[1]), dim3(kCollideThreads),
-                               sizeof(uint32_t) * 7 * c->lv_stride[1], c->stream, c->work[1], c->n_work[1],
-                               c->lv_stride[1]);
+        for (int k = 0; k < 2; ++k) {
+            int rc = k == 0 ? launch_collide<float>(c, 0) : launch_collide<double>(c, 1);
+            if (rc) return c->sticky = rc;
+        }
         if (c->n_active)
             hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, c->stream,
                                c->inst_ptrs, c->n_active);

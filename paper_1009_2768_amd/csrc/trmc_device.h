@@ -155,6 +155,30 @@ __device__ __forceinline__ uint32_t feistel_dec(uint32_t y, uint32_t half, uint4
     return (L << half) | R;
 }
 
+__device__ __forceinline__ uint32_t feistel_enc(uint32_t x, uint32_t half, uint4 k)
+{
+    const uint32_t mask = (half >= 32u) ? 0xFFFFFFFFu : ((1u << half) - 1u);
+    uint32_t L = x >> half, R = x & mask;
+    const uint32_t kk[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const uint32_t rk = kk[i & 3] ^ ((uint32_t)i * 0x9E3779B9u);
+        const uint32_t nl = R;
+        const uint32_t nr = L ^ (fmix32(R ^ rk) & mask);
+        L = nl;
+        R = nr;
+    }
+    return (L << half) | R;
+}
+
+// Slot of role index i.
+__device__ __forceinline__ uint32_t perm_forward(uint32_t i, uint32_t n, uint32_t half, uint4 k)
+{
+    uint32_t x = feistel_enc(i, half, k);
+    while (x >= n) x = feistel_enc(x, half, k);
+    return x;
+}
+
 __device__ __forceinline__ uint32_t perm_inverse(uint32_t s, uint32_t n, uint32_t half, uint4 k)
 {
     uint32_t y = feistel_dec(s, half, k);

@@ -14,7 +14,12 @@ enum : uint32_t { CELL_OVERFLOW = 1u };
 constexpr uint32_t kMaxDepth = 2048;     // largest m_cap accepted
 constexpr uint32_t kMaxSlabCells = 12288;  // LDS histogram of the sort
 constexpr uint32_t kSortTile = 4096;     // particles per tile of the counting sort
-constexpr uint32_t kCollideThreads = 256;
+constexpr uint32_t kTile = 8192;         // slots per tile of the tiled collision pipeline
+constexpr uint32_t kBigStateBytes = 1024; // per-cell state of the tiled pipeline (before its level arrays)
+constexpr uint32_t kCollideThreads = 512;
+constexpr uint32_t kSmallPerBlock = kCollideThreads / 64;  // wave-per-cell groups per workgroup
+constexpr uint32_t kSmallCell = 4096;  // cells expected to hold at most this many particles use one wave
+constexpr uint32_t kSmallDepth = 256;  // ... if their m_cap is at most this
 
 // Counters of one cell's last collision step.
 struct CellStats {
@@ -47,6 +52,8 @@ struct InstDev {
     uint64_t scratch_bpp;     // scratch bytes per particle
     uint64_t scratch_cpc;     // scratch bytes per cell
     uint32_t* error;          // context error word
+    double* tpart;            // tiled pipeline: [ceil(n / kTile)][8] partial sums
+    unsigned char* bigstate;  // tiled pipeline: state and level arrays between kernels
 };
 
 // One work item of the collision kernel: a cell of an instance.

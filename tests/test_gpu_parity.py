@@ -204,3 +204,18 @@ def test_moments_match_oracle(trmc, orc):
     m = o.moments()[0]
     for k, key in enumerate(["rho", "ux", "uy", "uz", "T", "Pxx", "Pyy", "Pzz", "M4"]):
         assert mom[key][0] == pytest.approx(m[k], rel=1e-12, abs=1e-13), key
+
+
+@pytest.mark.parametrize("n,eps,alpha,trunc,init", [
+    (65536, 0.3, 0.0, 1, "bkw"),       # 8 tiles, fixed depth
+    (40000, 0.05, 1.0, 2, "bimax"),    # ragged last tile, hard spheres, adaptive redo inside the cell kernel
+    (20000, 1e-3, 1.0, 2, "bimax"),    # fully thermalized
+    (9000, 5.0, 0.0, 0, "bkw"),        # nearly collisionless
+])
+def test_large_cells_tiled_pipeline(trmc, orc, n, eps, alpha, trunc, init):
+    say("large cell (tiled)", n, eps, alpha, trunc)
+    inst, a = homog(trmc, n, eps, alpha=alpha, trunc=trunc, m_init=2, m_cap=64, init=init, uid=21)
+    (got, mom), = run_gpu(trmc, [inst], [a], 3)
+    o = oracle_of(orc, inst, a)
+    o.run(3)
+    compare(o, got, mom, 1)
