@@ -101,6 +101,13 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--path", choices=["auto", "default", "group", "wave", "tiled"], default="auto",
+                    help="kernel path per cell: auto = autotuned per size bucket (outside the timed region)")
+    ap.add_argument("--table", default=None,
+                    help="fixed schedule instead of tuning, e.g. 8:wave,9:wave,11:group (bucket:path)")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one instead of a HIP graph")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB each (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -108,6 +115,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
+        return
 
     import paper_1009_2768_amd as T
     T.load()
@@ -118,6 +135,24 @@ def main():
     t0 = time.time()
     ctx, bufs = build_context(T, N, eps, alpha, init, args.seed, prec)
     log(f"context ready in {time.time() - t0:.1f} s")
+    names = ["default", "group", "wave", "tiled"]
+    if args.table:
+        table = [0] * T.SCHED_BUCKETS
+        for item in args.table.split(","):
+            b, name = item.split(":")
+            table[int(b)] = names.index(name)
+    elif args.path == "auto":
+        from paper_1009_2768_amd.autotune import autotune
+        t0 = time.time()
+        table, _ = autotune(ctx.instances, ctx._particles, log=log)
+        log(f"autotune done in {time.time() - t0:.1f} s")
+    else:
+        table = [names.index(args.path)] * T.SCHED_BUCKETS
+    ctx.set_schedule(table)
+    schedule = {f"2^{T.size_bucket(i)}": names[table[T.size_bucket(i)]] for i in ctx.instances}
+    schedule = dict(sorted(schedule.items(), key=lambda kv: int(kv[0][2:])))
+    if not args.no_graph:
+        ctx.use_graph(True)
     stream = ctx.stream
     for s in range(args.warmup):
         ctx.step(1)
@@ -158,7 +193,8 @@ def main():
         "config": {"workload": "batched homogeneous TRMC-R: 4096 instances, N log-uniform [256, 65536], "
                                "eps log-uniform [1e-4, 10], Maxwell/hard-sphere 50/50, adaptive depth m_cap 64, "
                                "dt 0.05",
-                   "instances": args.instances, "particles": total, "precision": args.precision},
+                   "instances": args.instances, "particles": total, "precision": args.precision,
+                   "schedule": schedule, "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_collide<float> (+ k_advance, about 2 us)"},

@@ -161,6 +161,28 @@ int trmc_admit(trmc_ctx* ctx, const trmc_desc* desc, const trmc_particles* buf, 
  * once the stream has passed this point). */
 int trmc_retire(trmc_ctx* ctx, uint32_t slot);
 
+/* Batching: the kernel path of each cell, chosen per bucket of the expected
+ * particles per cell p of its instance, bucket floor(log2(max(p, 1))) (32
+ * buckets).  paths[b] is one of the TRMC_PATH_* values below; n_buckets <= 32
+ * entries are read, the rest keep TRMC_PATH_DEFAULT.  A path a cell cannot take
+ * (WAVE or TILED with m_cap > 256, TILED for a slab cell) gives it the GROUP
+ * path.  Results do not depend on the schedule beyond the rounding order of the
+ * FP64 cell sums.  Synchronises the stream; TRMC_EINVAL on an unknown path. */
+#define TRMC_SCHED_BUCKETS 32
+#define TRMC_PATH_DEFAULT 0u /* library rule: TILED for homogeneous, WAVE for slab cells */
+#define TRMC_PATH_GROUP 1u   /* one 512-thread workgroup per cell */
+#define TRMC_PATH_WAVE 2u    /* one 64-lane wave per cell, eight cells per workgroup */
+#define TRMC_PATH_TILED 3u   /* tile kernels over the cell's slots plus per-cell tree kernels */
+int trmc_set_schedule(trmc_ctx* ctx, const uint32_t* paths, uint32_t n_buckets);
+
+/* Current schedule (n_buckets <= 32 entries written). */
+int trmc_get_schedule(const trmc_ctx* ctx, uint32_t* paths, uint32_t n_buckets);
+
+/* on != 0: trmc_step replays one captured HIP graph of the step's launches
+ * (captured on first use after the work tables change); on == 0: launches each
+ * kernel directly.  Both enqueue the same kernels with the same arguments. */
+int trmc_use_graph(trmc_ctx* ctx, int on);
+
 /* Wait for the stream and report any asynchronous error. */
 int trmc_sync(trmc_ctx* ctx);
 

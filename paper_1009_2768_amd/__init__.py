@@ -16,10 +16,12 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _abi
-from ._abi import (ADAPTIVE, FIXED, FP32_MIXED, FP64, HOMOG, NATURAL, SLAB1D, TrmcError, check)
+from ._abi import (ADAPTIVE, FIXED, FP32_MIXED, FP64, HOMOG, NATURAL, PATH_DEFAULT, PATH_GROUP, PATH_TILED,
+                   PATH_WAVE, SCHED_BUCKETS, SLAB1D, TrmcError, check)
 
 __all__ = ["Instance", "Context", "HOMOG", "SLAB1D", "FP64", "FP32_MIXED", "NATURAL", "FIXED", "ADAPTIVE",
-           "TrmcError", "load"]
+           "PATH_DEFAULT", "PATH_GROUP", "PATH_WAVE", "PATH_TILED", "SCHED_BUCKETS", "TrmcError", "load",
+           "size_bucket"]
 
 load = _abi.load
 
@@ -80,6 +82,16 @@ class Instance:
     @property
     def np_dtype(self):
         return np.float64 if self.precision == FP64 else np.float32
+
+
+def size_bucket(inst: Instance) -> int:
+    """Schedule bucket of an instance's cells: floor(log2) of the expected particles
+    per cell (the rule of trmc_set_schedule)."""
+    per = inst.n_particles / (inst.n_cells if inst.geometry == SLAB1D else 1)
+    b = 0
+    while b + 1 < SCHED_BUCKETS and per >= float(2 << b):
+        b += 1
+    return b
 
 
 def _stream_handle(stream):
@@ -157,6 +169,21 @@ class Context:
 
     def sync(self):
         check(self._lib.trmc_sync(self._ctx), "trmc_sync")
+
+    # -- batching ----------------------------------------------------------
+    def set_schedule(self, paths):
+        """Kernel path per size bucket (list of PATH_* values, at most SCHED_BUCKETS)."""
+        a = (ctypes.c_uint32 * max(1, len(paths)))(*[int(p) for p in paths])
+        check(self._lib.trmc_set_schedule(self._ctx, a, len(paths)), "trmc_set_schedule")
+
+    def get_schedule(self):
+        a = (ctypes.c_uint32 * SCHED_BUCKETS)()
+        check(self._lib.trmc_get_schedule(self._ctx, a, SCHED_BUCKETS), "trmc_get_schedule")
+        return list(a)
+
+    def use_graph(self, on: bool = True):
+        """Replay one captured HIP graph per step instead of launching each kernel."""
+        check(self._lib.trmc_use_graph(self._ctx, 1 if on else 0), "trmc_use_graph")
 
     # -- serving -----------------------------------------------------------
     def admit(self, inst: Instance, particles: dict) -> int:

@@ -16,8 +16,11 @@ CELL_OVERFLOW = 1
 EXPORTS = [
     "trmc_abi_version", "trmc_strerror", "trmc_workspace_size", "trmc_ctx_workspace_size", "trmc_init",
     "trmc_step", "trmc_moments", "trmc_state", "trmc_read", "trmc_admit", "trmc_retire", "trmc_sync",
-    "trmc_destroy",
+    "trmc_destroy", "trmc_set_schedule", "trmc_get_schedule", "trmc_use_graph",
 ]
+
+SCHED_BUCKETS = 32
+PATH_DEFAULT, PATH_GROUP, PATH_WAVE, PATH_TILED = 0, 1, 2, 3
 
 
 class Desc(ctypes.Structure):
@@ -96,6 +99,12 @@ def load():
     L.trmc_sync.restype = i
     L.trmc_destroy.argtypes = [vp]
     L.trmc_destroy.restype = i
+    L.trmc_set_schedule.argtypes = [vp, P(u32), u32]
+    L.trmc_set_schedule.restype = i
+    L.trmc_get_schedule.argtypes = [vp, P(u32), u32]
+    L.trmc_get_schedule.restype = i
+    L.trmc_use_graph.argtypes = [vp, i]
+    L.trmc_use_graph.restype = i
     _lib = L
     return L
 

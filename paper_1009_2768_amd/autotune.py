@@ -1,0 +1,82 @@
+"""Schedule autotuner for batched runs.
+
+The collision step has three kernel paths for a cell (one workgroup, one wave,
+or the tile pipeline; trmc_set_schedule).  Which is fastest depends on the cell
+size, the depth and the mix, so the tuner measures: the instances are grouped by
+schedule bucket (floor(log2) of particles per cell), and for every bucket each
+path the bucket's cells can take is timed on copies of that bucket's instances
+(a fresh copy per candidate, so every candidate steps the same states).  The
+result is a table for Context.set_schedule.  Results do not depend on the
+schedule, so tuning never changes what a run computes, only how fast.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import replace
+
+from . import (HOMOG, PATH_DEFAULT, PATH_GROUP, PATH_TILED, PATH_WAVE, SCHED_BUCKETS, Context, size_bucket)
+
+_SHALLOW = 256  # deepest m_cap of the wave and tile paths
+
+
+def candidates(insts) -> list[int]:
+    paths = [PATH_GROUP]
+    if all(i.m_cap <= _SHALLOW for i in insts):
+        paths.append(PATH_WAVE)
+        if all(i.geometry == HOMOG for i in insts):
+            paths.append(PATH_TILED)
+    return paths
+
+
+def _time_path(insts, parts, path, warmup, steps):
+    import torch
+    clones = [{k: (v.clone() if v is not None else None) for k, v in p.items()} for p in parts]
+    ctx = Context([replace(i) for i in insts], clones)
+    try:
+        ctx.set_schedule([path] * SCHED_BUCKETS)
+        ctx.step(warmup)
+        ctx.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(ctx.stream):
+            a.record(ctx.stream)
+            ctx.step(steps)
+            b.record(ctx.stream)
+        ctx.sync()
+        b.synchronize()
+        return a.elapsed_time(b) / steps
+    finally:
+        ctx.close()
+
+
+def autotune(instances, particles, warmup=1, steps=2, max_particles=8_000_000, log=None):
+    """Return (schedule table, per-bucket timings in ms) for these instances.
+
+    particles[i] holds the device tensors of instances[i]; they are copied, never
+    stepped.  At most max_particles particles of a bucket are used to time it.
+    """
+    buckets: dict[int, list[int]] = {}
+    for k, inst in enumerate(instances):
+        buckets.setdefault(size_bucket(inst), []).append(k)
+    table = [PATH_DEFAULT] * SCHED_BUCKETS
+    timings = {}
+    for b in sorted(buckets):
+        idx, tot = [], 0
+        for k in buckets[b]:
+            if idx and tot + instances[k].n_particles > max_particles:
+                break
+            idx.append(k)
+            tot += instances[k].n_particles
+        insts = [instances[k] for k in idx]
+        parts = [particles[k] for k in idx]
+        res = {}
+        t0 = time.perf_counter()
+        for path in candidates(insts):
+            res[path] = _time_path(insts, parts, path, warmup, steps)
+        best = min(res, key=res.get)
+        table[b] = best
+        timings[b] = res
+        if log:
+            log(f"bucket 2^{b}: {len(idx)} instances, {tot} particles: "
+                + ", ".join(f"{['default', 'group', 'wave', 'tiled'][p]} {t:.3f} ms" for p, t in res.items())
+                + f" -> {['default', 'group', 'wave', 'tiled'][best]} ({time.perf_counter() - t0:.1f} s)")
+    return table, timings

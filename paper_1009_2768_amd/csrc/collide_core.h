@@ -32,6 +32,22 @@ __device__ __forceinline__ void gsync()
     }
 }
 
+// Synchronisation of the group for LDS traffic only (global stores stay in
+// flight; they are ordered by a later gsync).
+template <int G>
+__device__ __forceinline__ void gsync_lds()
+{
+    if constexpr (G == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+}
+
 // Sum over the group; every thread receives the total.  Fixed order: butterfly
 // inside each wave, then the waves in order.  `red` holds (G/64) * K doubles.
 template <int G, int K>
@@ -46,12 +62,12 @@ __device__ __forceinline__ void gsum(double (&v)[K], double* red)
     }
     if constexpr (G > 64) {
         const int lane = threadIdx.x & 63, wave = (threadIdx.x % G) >> 6;
-        gsync<G>();
+        gsync_lds<G>();
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
         }
-        gsync<G>();
+        gsync_lds<G>();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double a = 0.0;
@@ -68,9 +84,9 @@ __device__ __forceinline__ double gmax(double v, double* red)
     for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     if constexpr (G > 64) {
         const int lane = threadIdx.x & 63, wave = (threadIdx.x % G) >> 6;
-        gsync<G>();
+        gsync_lds<G>();
         if (lane == 0) red[wave] = v;
-        gsync<G>();
+        gsync_lds<G>();
         double a = red[0];
         for (int w = 1; w < G / 64; ++w) a = fmax(a, red[w]);
         v = a;
@@ -85,9 +101,9 @@ __device__ __forceinline__ uint32_t gsum_u32(uint32_t v, uint32_t* red)
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
     if constexpr (G > 64) {
         const int lane = threadIdx.x & 63, wave = (threadIdx.x % G) >> 6;
-        gsync<G>();
+        gsync_lds<G>();
         if (lane == 0) red[wave] = v;
-        gsync<G>();
+        gsync_lds<G>();
         uint32_t a = 0;
         for (int w = 0; w < G / 64; ++w) a += red[w];
         v = a;
@@ -352,7 +368,7 @@ __device__ __forceinline__ void split_levels(const Key& key, uint32_t n, double 
             sh.attempts += 1;
         }
     }
-    gsync<G>();
+    gsync_lds<G>();
 }
 
 // b. Collision trees, deepest level first (Alg. 4.3 in level order).  Level l
@@ -375,7 +391,7 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
     for (;;) {
         const uint32_t me = sh.me;
         for (uint32_t l = tid; l <= me; l += G) L.run[l] = 0;
-        gsync<G>();
+        gsync_lds<G>();
         ncoll = 0;
         bool ovf = false;
         for (uint32_t l = me; l >= 1; --l) {
@@ -403,7 +419,7 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
                         gl.jbuf[4 * tid + 2] = (uint16_t)__umulhi(wv.z, l);
                         gl.jbuf[4 * tid + 3] = (uint16_t)__umulhi(wv.w, l);
                     }
-                    gsync<G>();
+                    gsync_lds<G>();
                     const uint32_t c = b0 + tid;
                     const bool valid = c < Cl;
                     const uint32_t j = valid ? (uint32_t)gl.jbuf[tid] : 0u;
@@ -431,7 +447,7 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
                     const unsigned long long Mrev = shfl64(myM, (int)(lane < l ? l - 1u - lane : 0u));
                     const uint32_t local = (uint32_t)(__popcll(Mj & lt) + __popcll(Mh & lt));
                     if (lane < l) gl.wcnt[wave][lane] = (uint32_t)(__popcll(myM) + __popcll(Mrev));
-                    gsync<G>();
+                    gsync_lds<G>();
                     if (tid < l) {
                         uint32_t acc = L.run[tid];
 #pragma unroll
@@ -441,13 +457,13 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
                         }
                         L.run[tid] = acc;
                     }
-                    gsync<G>();
+                    gsync_lds<G>();
                     if (valid) {
                         jarr[fst + c] = j;
                         rA[fst + c] = gl.wpre[wave][j] + local;
                         rB[fst + c] = gl.wpre[wave][h] + local + (j == h ? 1u : 0u);
                     }
-                    gsync<G>();
+                    gsync_lds<G>();
                 }
             } else {
                 // deep levels (natural depth): one wave, distinct target levels by ballot
@@ -489,24 +505,24 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
                         }
                     }
                 }
-                gsync<G>();
+                gsync_lds<G>();
             }
             ncoll += Cl;
         }
         if (ovf) {
             if (tid == 0) sh.overflow = 1u;
-            gsync<G>();
+            gsync_lds<G>();
             return ncoll;
         }
         if (tid == 0) sh.R0 = L.run[0];
-        gsync<G>();
+        gsync_lds<G>();
         if (sh.R0 <= n) break;
         if (tid == 0) {
             L.N[me] += L.N[me + 1];
             sh.me = me - 1u;
             sh.folds += 1;
         }
-        gsync<G>();
+        gsync_lds<G>();
     }
     return ncoll;
 }
@@ -585,7 +601,11 @@ __device__ __forceinline__ void gather_range(const T* vx, const T* vy, const T* 
 // d. Collisions, shallowest level first; all collisions of a level in parallel
 //    (eq. Maxwell_coll-r, eq. n3d-r; Alg. 4.4 acceptance).  Final r goes to the
 //    slot of leaf r.  Per-thread counters and the finals' sum of (vx-m)^2.
-template <typename T, int G>
+//    Leaves come from M.leaf, indexed by leaf rank (ByRole = false, gathered by
+//    the whole-cell kernel) or by role index (ByRole = true: M.leaf is then the
+//    cell's role-ordered copy, leaf r being role N0 + r, or N0 - 1 - (r - P)
+//    for a borrowed one).
+template <typename T, int G, bool ByRole>
 __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const Levels& L, const CellShared& sh,
                                           const CellMem<T>& M, unsigned long long ncoll, T alpha, T gT, double mx,
                                           uint32_t tid, uint32_t& dummies, uint32_t& viol, double& sfin)
@@ -608,13 +628,15 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const Leve
             const uint32_t ra = M.rA[id], rb = M.rB[id];
             Vec3<T> a, b;
             if (j == 0) {
-                a = Vec3<T>{M.leaf[ra], M.leaf[n + ra], M.leaf[2 * n + ra]};
+                const uint32_t q = ByRole ? (ra < P ? N0 + ra : N0 - 1u - (ra - P)) : ra;
+                a = Vec3<T>{M.leaf[q], M.leaf[n + q], M.leaf[2 * n + q]};
             } else {
                 const uint64_t p = (uint64_t)L.outoff[j] + ra;
                 a = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
             }
             if (h == 0) {
-                b = Vec3<T>{M.leaf[rb], M.leaf[n + rb], M.leaf[2 * n + rb]};
+                const uint32_t q = ByRole ? (rb < P ? N0 + rb : N0 - 1u - (rb - P)) : rb;
+                b = Vec3<T>{M.leaf[q], M.leaf[n + q], M.leaf[2 * n + q]};
             } else {
                 const uint64_t p = (uint64_t)L.outoff[h] + rb;
                 b = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
@@ -690,6 +712,56 @@ __device__ __forceinline__ void decide(InstDev* I, uint32_t cell, uint32_t n, co
         }
     }
     sh.decision = decision;
+}
+
+// Sums over the roles [lo, hi) of a cell from its role-ordered copy vr (3 x n)
+// and its block sums bs (kRoleBlock roles per block, 8 doubles each: sum of
+// v - m (3), of (vx - m)^2, of |v - m|^2), with the cell mean m: whole blocks
+// from bs, the partial blocks at both ends from vr.  This thread's share in
+// out[5]; the caller reduces over the group.
+template <typename T, int G>
+__device__ __forceinline__ void range_sums(const T* vr, const double* bs, uint32_t n, uint32_t lo, uint32_t hi,
+                                           double mx, double my, double mz, uint32_t tid, double (&out)[5])
+{
+    if (lo >= hi) return;
+    const uint32_t b_lo = (lo + kRoleBlock - 1) / kRoleBlock, b_hi = hi / kRoleBlock;
+    auto add_one = [&](uint32_t i) {
+        const double dx = (double)vr[i] - mx, dy = (double)vr[n + i] - my, dz = (double)vr[2 * n + i] - mz;
+        out[0] += dx;
+        out[1] += dy;
+        out[2] += dz;
+        out[3] += dx * dx;
+        out[4] += dx * dx + dy * dy + dz * dz;
+    };
+    if (b_lo >= b_hi) {  // inside one block
+        for (uint32_t i = lo + tid; i < hi; i += G) add_one(i);
+        return;
+    }
+    for (uint32_t i = lo + tid; i < b_lo * kRoleBlock; i += G) add_one(i);
+    for (uint32_t i = b_hi * kRoleBlock + tid; i < hi; i += G) add_one(i);
+    for (uint32_t b = b_lo + tid; b < b_hi; b += G) {
+        const double* p = bs + 8ull * b;
+        out[0] += p[0];
+        out[1] += p[1];
+        out[2] += p[2];
+        out[3] += p[3];
+        out[4] += p[4];
+    }
+}
+
+// Sums of an attempt from the role-ordered copy: all = {kept (vx-m)^2, th
+// (vx-m)^2, th v-m (3), th |v-m|^2, (finals, filled by the caller)}.
+template <typename T, int G>
+__device__ __forceinline__ void attempt_sums(const T* vr, const double* bs, uint32_t n, uint32_t kept_end,
+                                             uint32_t leaf_end, double mx, double my, double mz, uint32_t tid,
+                                             double* red, double (&all)[7])
+{
+    double k5[5] = {0, 0, 0, 0, 0}, t5[5] = {0, 0, 0, 0, 0};
+    range_sums<T, G>(vr, bs, n, 0u, kept_end, mx, my, mz, tid, k5);
+    range_sums<T, G>(vr, bs, n, leaf_end, n, mx, my, mz, tid, t5);
+    double v[6] = {k5[3], t5[3], t5[0], t5[1], t5[2], t5[4]};
+    gsum<G, 6>(v, red);
+    for (int q = 0; q < 6; ++q) all[q] = v[q];
 }
 
 __device__ __forceinline__ void write_stats(CellStats* st, uint32_t n, const CellShared& sh)

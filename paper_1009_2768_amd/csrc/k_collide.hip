@@ -207,7 +207,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
 
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
-        bottom_up<T, G>(key, n, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
+        bottom_up<T, G, false>(key, n, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
         TRMC_PHASE(4);
 
         double all[7] = {sums[0], sums[1], sums[2], sums[3], sums[4], sums[5], sfin};

@@ -1,15 +1,17 @@
-// k_tiled.hip -- the collision step of large homogeneous cells as a pipeline of
+// k_tiled.hip -- the collision step of homogeneous cells as a pipeline of
 // lean streaming kernels over fixed tiles of kTile slots (high occupancy, many
 // loads in flight) around per-cell kernels for the parts that need the whole
 // cell (the trees and the collisions):
 //
-//   k_tile_prep    tiles: role of every slot (keyed permutation), partial sums
-//   k_tile_dv      tiles: max |v - mean|^2 for the VHS majorant
-//   k_big_tree     cells: moments, tau, split (Alg. 4.2), trees (Alg. 4.3)
-//   k_tile_gather  tiles: leaves, partial sums of the unchanged / thermalized sets
-//   k_big_collide  cells: collisions level by level, adaptive test (Sec. 4.3);
-//                  a rejected attempt is redone inside, tile by tile, with the
-//                  same tile sums as k_tile_gather
+//   k_tile_prep    tiles: role of every slot (keyed permutation), the cell's
+//                  role-ordered copy, partial sums for the mean
+//   k_tile_bsum    tiles: sums over blocks of roles; max |v - mean|^2 (VHS majorant)
+//   k_big_split    cells: moments, tau, split (Alg. 4.2); light / heavy lists
+//   k_big_tree     cells: collision trees (Alg. 4.3)
+//   k_big_collide  cells: sums of the unchanged / thermalized sets from block
+//                  sums, collisions level by level (leaves read from the
+//                  role-ordered copy), adaptive test (Sec. 4.3); a rejected
+//                  attempt is redone inside
 //   k_tile_zsum    tiles: sums of the Maxwellian normals of the thermalized set
 //   k_tile_write   tiles: leaves take the finals, thermalized slots the rescaled
 //                  Maxwellian samples (normals drawn again from their keys)
@@ -70,8 +72,9 @@ struct CellView {
 
 template <typename T>
 __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ bigs, const uint32_t* __restrict__ prefix,
-                                                   uint32_t nb)
+                                                   uint32_t nb, uint32_t* __restrict__ list_count)
 {
+    if (blockIdx.x == 0 && threadIdx.x < 2u) list_count[threadIdx.x] = 0u;  // lists of this step
     __shared__ double t_red[(kTT / 64) * 8];
     uint32_t b, k;
     tile_of(prefix, nb, blockIdx.x, b, k);
@@ -81,7 +84,10 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
     const Key key{V.I->seed, V.I->uid, 0u, V.I->step};
     const uint4 pk = draw(key, 0, TAG_PERM, 0);
     const uint32_t half = perm_half(n);
-    uint32_t* role = reinterpret_cast<uint32_t*>(V.I->scratch);
+    CellMem<T> M;
+    M.init(V.I, 0, 0, n);
+    uint32_t* role = M.role;
+    T* vr = M.leaf;  // role-ordered copy of the cell
     const double c0 = (double)V.vx[0];
     constexpr int U = 4;
     double s[4] = {0, 0, 0, 0};
@@ -113,7 +119,11 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
                 s[1] += (double)ay[u];
                 s[2] += (double)az[u];
                 s[3] += dx * dx;
-                role[i] = perm_inverse(i, n, half, pk);
+                const uint32_t r = perm_inverse(i, n, half, pk);
+                role[i] = r;
+                vr[r] = ax[u];
+                vr[n + r] = ay[u];
+                vr[2 * n + r] = az[u];
             }
         }
 #pragma unroll
@@ -155,65 +165,104 @@ __device__ __forceinline__ void cell_mean(const InstDev* I, uint32_t n, double c
     Sn = sn > 0.0 ? sn : 0.0;
 }
 
+// Sums over blocks of kRoleBlock roles of the role-ordered copy, centred on the
+// cell mean (sum of v - m, of (vx - m)^2, of |v - m|^2), and for VHS the tile's
+// max |v - m|^2.  Any role range's sums are then a few block sums plus two
+// partial blocks (range_sums), so the attempts of the adaptive test cost
+// O(n / kRoleBlock) instead of a pass over the cell.
 template <typename T>
-__global__ __launch_bounds__(kTT) void k_tile_dv(const CellRef* __restrict__ bigs, const uint32_t* __restrict__ prefix,
-                                                 uint32_t nb)
+__global__ __launch_bounds__(kTT) void k_tile_bsum(const CellRef* __restrict__ bigs, const uint32_t* __restrict__ prefix,
+                                                   uint32_t nb)
 {
     __shared__ double t_red[(kTT / 64) * 8];
+    __shared__ double mean[3];
     uint32_t b, k;
     tile_of(prefix, nb, blockIdx.x, b, k);
     CellView<T> V(bigs[b].inst);
-    if (V.I->alpha == 0.0) return;
     const uint32_t n = V.n;
-    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
-    __shared__ double mean[3];
     if (threadIdx.x == 0) {
         double Sn;
         cell_mean(V.I, n, (double)V.vx[0], mean[0], mean[1], mean[2], Sn);
     }
     __syncthreads();
     const double mx = mean[0], my = mean[1], mz = mean[2];
-    constexpr int U = 4;
+    CellMem<T> M;
+    M.init(V.I, 0, 0, n);
+    const T* vr = M.leaf;
+    const uint32_t r_begin = k * kTile, r_end = (r_begin + kTile < n) ? r_begin + kTile : n;
     double d2max = 0.0;
-    for (uint32_t s0 = s_begin + threadIdx.x; s0 < s_end; s0 += kTT * U) {
-        T ax[U], ay[U], az[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t i = s0 + u * kTT;
-            const bool ok = i < s_end;
-            ax[u] = ok ? V.vx[i] : T(0);
-            ay[u] = ok ? V.vy[i] : T(0);
-            az[u] = ok ? V.vz[i] : T(0);
+    for (uint32_t b0 = r_begin; b0 < r_end; b0 += kRoleBlock) {
+        const uint32_t b1 = (b0 + kRoleBlock < r_end) ? b0 + kRoleBlock : r_end;
+        double sv[5] = {0, 0, 0, 0, 0};
+        for (uint32_t i = b0 + threadIdx.x; i < b1; i += kTT) {
+            const double dx = (double)vr[i] - mx, dy = (double)vr[n + i] - my, dz = (double)vr[2 * n + i] - mz;
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            sv[0] += dx;
+            sv[1] += dy;
+            sv[2] += dz;
+            sv[3] += dx * dx;
+            sv[4] += d2;
+            d2max = d2 > d2max ? d2 : d2max;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (s0 + u * kTT < s_end) {
-                const double dx = (double)ax[u] - mx, dy = (double)ay[u] - my, dz = (double)az[u] - mz;
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                d2max = d2 > d2max ? d2 : d2max;
-            }
+        gsum<kTT, 5>(sv, t_red);
+        if (threadIdx.x == 0) {
+            double* p = V.I->bsum + 8ull * (b0 / kRoleBlock);
+            for (int q = 0; q < 5; ++q) p[q] = sv[q];
         }
     }
-    d2max = gmax<kTT>(d2max, t_red);
-    if (threadIdx.x == 0) V.I->tpart[8ull * k + 4] = d2max;
+    if (V.I->alpha != 0.0) {
+        d2max = gmax<kTT>(d2max, t_red);
+        if (threadIdx.x == 0) V.I->tpart[8ull * k + 4] = d2max;
+    }
 }
 
-// Per-cell kernels: one workgroup of kTT threads per large cell.
+// ---------------------------------------------------------------------------
+// Per-cell kernels.  k_big_split runs one wave per cell and sorts the cells by
+// the size of their trees: "light" cells (expected collisions at most
+// kHeavyColl) are then processed one wave per cell, eight per workgroup, with
+// no workgroup barriers, so that many cells' level-by-level chains overlap on a
+// CU; "heavy" cells get a whole workgroup.  The lists are in device memory:
+// list[0..count[0]) light, list[cap..cap+count[1]) heavy (order of arrival does
+// not matter: every cell's arithmetic is its own).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kHeavyColl = 1536;
+
+struct CellLists {
+    uint32_t* list;   // [2 * cap]
+    uint32_t* count;  // [2]
+    uint32_t cap;
+};
+
+// Group G of cell to process: light cells by wave, heavy cells by workgroup.
+template <int G>
+__device__ __forceinline__ bool pick_cell(const CellLists& cl, uint32_t& b)
+{
+    if constexpr (G == 64) {
+        const uint32_t idx = blockIdx.x * (kTT / 64) + (threadIdx.x >> 6);
+        if (idx >= cl.count[0]) return false;
+        b = cl.list[idx];
+    } else {
+        if (blockIdx.x >= cl.count[1]) return false;
+        b = cl.list[cl.cap + blockIdx.x];
+    }
+    return true;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kTT) void k_big_tree(const CellRef* __restrict__ bigs, uint32_t nb, uint32_t lv_stride)
+__global__ __launch_bounds__(kTT) void k_big_split(const CellRef* __restrict__ bigs, uint32_t nb, uint32_t lv_stride,
+                                                   CellLists cl)
 {
     extern __shared__ uint32_t lds_levels[];
-    __shared__ GroupLds<kTT> gl;
-    if (blockIdx.x >= nb) return;
-    InstDev* I = bigs[blockIdx.x].inst;
+    __shared__ CellShared shs[kTT / 64];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t b = blockIdx.x * (kTT / 64) + wave;
+    if (b >= nb) return;
+    InstDev* I = bigs[b].inst;
     const uint32_t n = I->cell_off[1] - I->cell_off[0];
-    CellShared& sh = gl.sh;
-    const uint32_t tid = threadIdx.x;
+    CellShared& sh = shs[wave];
     const Key key{I->seed, I->uid, 0u, I->step};
-    CellMem<T> M;
-    M.init(I, 0, 0, n);
-    Levels L = levels_at(lds_levels, lv_stride);
-    if (tid == 0) {
+    Levels L = levels_at(lds_levels + (size_t)wave * 5u * lv_stride, lv_stride);
+    if (lane == 0) {
         const T* vx = reinterpret_cast<const T*>(I->vx[0]);
         cell_mean(I, n, (double)vx[0], sh.mean[0], sh.mean[1], sh.mean[2], sh.Sn);
         double dmax = 0.0;
@@ -222,63 +271,86 @@ __global__ __launch_bounds__(kTT) void k_big_tree(const CellRef* __restrict__ bi
             for (uint32_t t = 0; t < nt; ++t) dmax = fmax(dmax, I->tpart[8ull * t + 4]);
         }
         cell_params(I, 0, n, dmax, sh);
+        sh.overflow = n < 2 ? 1u : 0u;  // cells of fewer than 2 particles are skipped
     }
-    gsync<kTT>();
-    split_levels<kTT>(key, n, sh.q, L, sh, tid);
-    const unsigned long long ncoll = build_trees<kTT>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
-    if (!sh.overflow) level_offsets<kTT>(n, ncoll, M.ocap, L, sh, tid);
-    // keep the state and the level arrays for the next kernels
+    gsync<64>();
+    if (n >= 2) split_levels<64>(key, n, sh.q, L, sh, lane);
+    // expected collisions of the trees: a level-k sample costs H_k / 2 of them
+    double est = 0.0, Hk = 0.0;
+    if (n >= 2)
+        for (uint32_t k = 1; k <= sh.me; ++k) {
+            Hk += 1.0 / (double)k;
+            est += 0.5 * Hk * (double)L.N[k];
+        }
     BigState* S = big_state(I);
     uint32_t* gL = big_levels(I);
-    for (uint32_t i = tid; i < 5u * lv_stride; i += kTT) gL[i] = lds_levels[i];
+    for (uint32_t i = lane; i < 5u * lv_stride; i += 64u) gL[i] = L.N[i];
+    if (lane == 0) {
+        S->sh = sh;
+        S->ncoll = 0;
+        if (n >= 2) {
+            const uint32_t heavy = est > (double)kHeavyColl ? 1u : 0u;
+            const uint32_t idx = atomicAdd(&cl.count[heavy], 1u);
+            cl.list[heavy * cl.cap + idx] = b;
+        } else {
+            CellStats s{};
+            s.n = n;
+            s.m_used = I->m_state[0];
+            *I->stats = s;
+        }
+    }
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(kTT) void k_big_tree(const CellRef* __restrict__ bigs, uint32_t lv_stride, CellLists cl)
+{
+    extern __shared__ uint32_t lds_levels[];
+    __shared__ GroupLds<G> glds[kTT / G];
+    uint32_t b;
+    if (!pick_cell<G>(cl, b)) return;
+    const uint32_t grp = threadIdx.x / G, tid = threadIdx.x % G;
+    GroupLds<G>& gl = glds[grp];
+    CellShared& sh = gl.sh;
+    InstDev* I = bigs[b].inst;
+    const uint32_t n = I->cell_off[1] - I->cell_off[0];
+    const Key key{I->seed, I->uid, 0u, I->step};
+    CellMem<T> M;
+    M.init(I, 0, 0, n);
+    uint32_t* lv = lds_levels + (size_t)grp * 5u * lv_stride;
+    Levels L = levels_at(lv, lv_stride);
+    BigState* S = big_state(I);
+    uint32_t* gL = big_levels(I);
+    for (uint32_t i = tid; i < lv_stride; i += G) lv[i] = gL[i];  // N[] of the split
+    if (tid == 0) sh = S->sh;
+    gsync<G>();
+    const unsigned long long ncoll = build_trees<G>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
+    if (!sh.overflow) level_offsets<G>(n, ncoll, M.ocap, L, sh, tid);
+    for (uint32_t i = tid; i < 5u * lv_stride; i += G) gL[i] = lv[i];
     if (tid == 0) {
         S->sh = sh;
         S->ncoll = ncoll;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kTT) void k_tile_gather(const CellRef* __restrict__ bigs,
-                                                     const uint32_t* __restrict__ prefix, uint32_t nb)
-{
-    __shared__ double t_red[(kTT / 64) * 8];
-    uint32_t b, k;
-    tile_of(prefix, nb, blockIdx.x, b, k);
-    CellView<T> V(bigs[b].inst);
-    const uint32_t n = V.n;
-    const BigState* S = big_state(V.I);
-    if (S->sh.overflow) return;
-    const uint32_t N0 = S->sh.N0, R0 = S->sh.R0, borrowed = S->sh.borrowed, P = n - N0;
-    const uint32_t kept_end = N0 - borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
-    CellMem<T> M;
-    M.init(V.I, 0, 0, n);
-    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
-    double sums[6] = {0, 0, 0, 0, 0, 0};
-    gather_range<T, kTT>(V.vx, V.vy, V.vz, M.role, M.leaf, n, s_begin, s_end, N0, kept_end, leaf_end,
-                         S->sh.mean[0], S->sh.mean[1], S->sh.mean[2], threadIdx.x, sums);
-    gsum<kTT, 6>(sums, t_red);
-    if (threadIdx.x == 0) {
-        double* tp = V.I->tpart + 8ull * k;
-        for (int q = 0; q < 6; ++q) tp[q] = sums[q];
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__ bigs, uint32_t nb, uint32_t lv_stride)
+template <typename T, int G>
+__global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__ bigs, uint32_t lv_stride,
+                                                     CellLists cl)
 {
     extern __shared__ uint32_t lds_levels[];
-    __shared__ GroupLds<kTT> gl;
-    __shared__ double tsum[6];
-    if (blockIdx.x >= nb) return;
-    InstDev* I = bigs[blockIdx.x].inst;
-    const uint32_t n = I->cell_off[1] - I->cell_off[0];
-    const uint32_t tid = threadIdx.x;
+    __shared__ GroupLds<G> glds[kTT / G];
+    uint32_t b;
+    if (!pick_cell<G>(cl, b)) return;
+    const uint32_t grp = threadIdx.x / G, tid = threadIdx.x % G;
+    GroupLds<G>& gl = glds[grp];
     CellShared& sh = gl.sh;
+    InstDev* I = bigs[b].inst;
+    const uint32_t n = I->cell_off[1] - I->cell_off[0];
     BigState* S = big_state(I);
     uint32_t* gL = big_levels(I);
-    for (uint32_t i = tid; i < 5u * lv_stride; i += kTT) lds_levels[i] = gL[i];
+    uint32_t* lv = lds_levels + (size_t)grp * 5u * lv_stride;
+    for (uint32_t i = tid; i < 5u * lv_stride; i += G) lv[i] = gL[i];
     if (tid == 0) sh = S->sh;
-    gsync<kTT>();
+    gsync<G>();
     CellStats* st = I->stats;
     if (sh.overflow) {
         if (tid == 0) {
@@ -292,58 +364,38 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
         return;
     }
     const Key key{I->seed, I->uid, 0u, I->step};
-    const T* vx = reinterpret_cast<const T*>(I->vx[0]);
-    const T* vy = reinterpret_cast<const T*>(I->vy[0]);
-    const T* vz = reinterpret_cast<const T*>(I->vz[0]);
     CellMem<T> M;
     M.init(I, 0, 0, n);
-    Levels L = levels_at(lds_levels, lv_stride);
+    Levels L = levels_at(lv, lv_stride);
     const double mx = sh.mean[0], my = sh.mean[1], mz = sh.mean[2];
     const T alpha = (T)I->alpha;
     const T gT = (T)sh.g;
-    const uint32_t nt = (n + kTile - 1) / kTile;
     unsigned long long ncoll = S->ncoll;
-    // sums of the first attempt from k_tile_gather, in tile order
-    if (tid == 0) {
-        for (int q = 0; q < 6; ++q) tsum[q] = 0.0;
-        for (uint32_t t = 0; t < nt; ++t)
-            for (int q = 0; q < 6; ++q) tsum[q] += I->tpart[8ull * t + q];
-    }
-    gsync<kTT>();
     for (;;) {
+        // sums of the unchanged and thermalized sets of this attempt
+        const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
+        const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
+        double all[7];
+        attempt_sums<T, G>(M.leaf, I->bsum, n, kept_end, leaf_end, mx, my, mz, tid, gl.red, all);
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
-        bottom_up<T, kTT>(key, n, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
+        bottom_up<T, G, true>(key, n, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
         double fs[1] = {sfin};
-        gsum<kTT, 1>(fs, gl.red);
-        const uint32_t td = gsum_u32<kTT>(dummies, gl.redu);
-        const uint32_t tv = gsum_u32<kTT>(viol, gl.redu);
+        gsum<G, 1>(fs, gl.red);
+        const uint32_t td = gsum_u32<G>(dummies, gl.redu);
+        const uint32_t tv = gsum_u32<G>(viol, gl.redu);
         if (tid == 0) {
-            const double all[7] = {tsum[0], tsum[1], tsum[2], tsum[3], tsum[4], tsum[5], fs[0]};
+            all[6] = fs[0];
             sh.dummies = td;
             sh.viol = tv;
             decide(I, 0, n, all, mx, my, mz, sh);
         }
-        gsync<kTT>();
+        gsync<G>();
         if (sh.decision) break;
-        // redo at depth sh.m: trees, then the tile sums exactly as k_tile_gather forms them
-        split_levels<kTT>(key, n, sh.q, L, sh, tid);
-        ncoll = build_trees<kTT>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
-        if (sh.overflow || !level_offsets<kTT>(n, ncoll, M.ocap, L, sh, tid)) break;
-        const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
-        const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
-        if (tid == 0)
-            for (int q = 0; q < 6; ++q) tsum[q] = 0.0;
-        for (uint32_t t = 0; t < nt; ++t) {
-            const uint32_t s_begin = t * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
-            double sums[6] = {0, 0, 0, 0, 0, 0};
-            gather_range<T, kTT>(vx, vy, vz, M.role, M.leaf, n, s_begin, s_end, N0, kept_end, leaf_end, mx, my, mz,
-                                 tid, sums);
-            gsum<kTT, 6>(sums, gl.red);
-            if (tid == 0)
-                for (int q = 0; q < 6; ++q) tsum[q] += sums[q];
-        }
-        gsync<kTT>();
+        // redo at depth sh.m
+        split_levels<G>(key, n, sh.q, L, sh, tid);
+        ncoll = build_trees<G>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
+        if (sh.overflow || !level_offsets<G>(n, ncoll, M.ocap, L, sh, tid)) break;
     }
     if (tid == 0) {
         if (sh.overflow) {
@@ -455,11 +507,13 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
 }
 
 #define TRMC_TILED_INSTANTIATE(T)                                                              \
-    template __global__ void k_tile_prep<T>(const CellRef*, const uint32_t*, uint32_t);        \
-    template __global__ void k_tile_dv<T>(const CellRef*, const uint32_t*, uint32_t);          \
-    template __global__ void k_big_tree<T>(const CellRef*, uint32_t, uint32_t);                \
-    template __global__ void k_tile_gather<T>(const CellRef*, const uint32_t*, uint32_t);      \
-    template __global__ void k_big_collide<T>(const CellRef*, uint32_t, uint32_t);             \
+    template __global__ void k_tile_prep<T>(const CellRef*, const uint32_t*, uint32_t, uint32_t*); \
+    template __global__ void k_tile_bsum<T>(const CellRef*, const uint32_t*, uint32_t);        \
+    template __global__ void k_big_split<T>(const CellRef*, uint32_t, uint32_t, CellLists);    \
+    template __global__ void k_big_tree<T, 64>(const CellRef*, uint32_t, CellLists);           \
+    template __global__ void k_big_tree<T, kTT>(const CellRef*, uint32_t, CellLists);          \
+    template __global__ void k_big_collide<T, 64>(const CellRef*, uint32_t, CellLists);        \
+    template __global__ void k_big_collide<T, kTT>(const CellRef*, uint32_t, CellLists);       \
     template __global__ void k_tile_zsum<T>(const CellRef*, const uint32_t*, uint32_t);        \
     template __global__ void k_tile_write<T>(const CellRef*, const uint32_t*, uint32_t);
 TRMC_TILED_INSTANTIATE(float)

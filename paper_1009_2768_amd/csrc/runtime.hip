@@ -24,16 +24,21 @@ template <typename T>
 __global__ void k_scatter(InstDev*);
 template <typename T>
 __global__ void k_moments(const CellRef*, uint32_t);
+struct CellLists {
+    uint32_t* list;
+    uint32_t* count;
+    uint32_t cap;
+};
 template <typename T>
-__global__ void k_tile_prep(const CellRef*, const uint32_t*, uint32_t);
+__global__ void k_tile_prep(const CellRef*, const uint32_t*, uint32_t, uint32_t*);
 template <typename T>
-__global__ void k_tile_dv(const CellRef*, const uint32_t*, uint32_t);
+__global__ void k_tile_bsum(const CellRef*, const uint32_t*, uint32_t);
 template <typename T>
-__global__ void k_big_tree(const CellRef*, uint32_t, uint32_t);
-template <typename T>
-__global__ void k_tile_gather(const CellRef*, const uint32_t*, uint32_t);
-template <typename T>
-__global__ void k_big_collide(const CellRef*, uint32_t, uint32_t);
+__global__ void k_big_split(const CellRef*, uint32_t, uint32_t, CellLists);
+template <typename T, int G>
+__global__ void k_big_tree(const CellRef*, uint32_t, CellLists);
+template <typename T, int G>
+__global__ void k_big_collide(const CellRef*, uint32_t, CellLists);
 template <typename T>
 __global__ void k_tile_zsum(const CellRef*, const uint32_t*, uint32_t);
 template <typename T>
@@ -56,7 +61,7 @@ uint32_t sort_tile_h(uint32_t n_cells)
 }
 
 struct Layout {
-    size_t inst, refs, eps, off, mstate, stats, mom, hist, bx, bvx, bvy, bvz, tpart, big, scratch, total;
+    size_t inst, refs, eps, off, mstate, stats, mom, hist, bx, bvx, bvy, bvz, tpart, bsum, big, scratch, total;
     uint32_t n_tiles;
 };
 
@@ -86,6 +91,7 @@ Layout layout_of(const trmc_desc& d)
     } else {
         // tiled pipeline of large homogeneous cells: tile sums, state and level arrays
         L.tpart = p; p += al(sizeof(double) * 8 * ((n + kTile - 1) / kTile));
+        L.bsum = p;  p += al(sizeof(double) * 8 * ((n + kRoleBlock - 1) / kRoleBlock));
         L.big = p;   p += al(kBigStateBytes + sizeof(uint32_t) * 5 * ((size_t)d.m_cap + 2));
     }
     L.scratch = p;
@@ -150,11 +156,20 @@ struct trmc_ctx {
     uint32_t lv_stride[2][3] = {{2, 2, 2}, {2, 2, 2}};
     uint32_t* tile_prefix[2] = {nullptr, nullptr};  // [n_work[k][2] + 1] first tile of each tiled cell
     uint32_t n_tiles[2] = {0, 0};
+    uint32_t* cls_list[2] = {nullptr, nullptr};   // [2 * max_cells] light / heavy cells of the step
+    uint32_t* cls_count[2] = {nullptr, nullptr};  // [2]
     InstDev** inst_ptrs = nullptr;
     uint32_t n_active = 0;
     uint32_t cells_used = 0;
     std::vector<Slot> slots;
     int sticky = 0;
+    uint32_t sched[TRMC_SCHED_BUCKETS] = {};  // TRMC_PATH_* per bucket of cell size
+    // captured step: every launch of one step, replayed by trmc_step
+    bool use_graph = false;
+    bool graph_dirty = true;
+    hipStream_t cap_stream = nullptr;  // stream the step is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -162,16 +177,18 @@ namespace {
 size_t ctx_bytes(uint32_t max_inst, uint32_t max_cells)
 {
     return al(sizeof(uint32_t)) + 6 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
-           2 * al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1)) + al(sizeof(InstDev*) * std::max(1u, max_inst));
+           2 * al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1)) +
+           2 * (al(sizeof(uint32_t) * 2 * std::max(1u, max_cells)) + al(2 * sizeof(uint32_t))) +
+           al(sizeof(InstDev*) * std::max(1u, max_inst));
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? 0 : TRMC_EIO; }
 
-// Rebuild the device work lists and the instance list.  Homogeneous cells of
-// more than kSmallCell particles take the tiled pipeline; cells expected to hold
-// at most kSmallCell particles (with m_cap <= kSmallDepth, which bounds their
-// level arrays in LDS) take one wave each; the others one workgroup each.  Lists
-// are ordered by expected size, largest first.
+// Rebuild the device work lists and the instance list.  The path of a cell comes
+// from the schedule bucket of its expected size; WAVE and TILED need m_cap <=
+// kSmallDepth (which bounds the level arrays of eight cells in LDS) and TILED a
+// homogeneous cell, else the cell takes GROUP.  Lists are ordered by expected
+// size, largest first.
 int rebuild_tables(trmc_ctx* c)
 {
     std::vector<std::pair<double, CellRef>> order[2][3];
@@ -184,10 +201,15 @@ int rebuild_tables(trmc_ctx* c)
         const bool slab = s.desc.geometry == TRMC_SLAB1D;
         const uint32_t nc = slab ? s.desc.n_cells : 1u;
         const double per = (double)s.desc.n_particles / nc;
-        int cls;
-        if (!slab && per > (double)kSmallCell) cls = 2;
-        else if (per <= (double)kSmallCell && s.desc.m_cap <= kSmallDepth) cls = 1;
-        else cls = 0;
+        uint32_t bucket = 0;
+        while (bucket + 1 < TRMC_SCHED_BUCKETS && per >= (double)(2ull << bucket)) ++bucket;
+        uint32_t path = c->sched[bucket];
+        if (path == TRMC_PATH_DEFAULT) path = slab ? (per <= (double)kSmallCell ? TRMC_PATH_WAVE : TRMC_PATH_GROUP)
+                                                   : TRMC_PATH_TILED;
+        const bool shallow = s.desc.m_cap <= kSmallDepth;
+        int cls = 0;
+        if (path == TRMC_PATH_TILED && !slab && shallow) cls = 2;
+        else if (path == TRMC_PATH_WAVE && shallow) cls = 1;
         for (uint32_t cc = 0; cc < nc; ++cc) order[k][cls].push_back({per, CellRef{s.dev, cc, 0}});
         stride[k][cls] = std::max(stride[k][cls], s.desc.m_cap + 2u);
     }
@@ -224,6 +246,7 @@ int rebuild_tables(trmc_ctx* c)
         if (e != hipSuccess) return TRMC_EIO;
     }
     c->n_active = (uint32_t)ptrs.size();
+    c->graph_dirty = true;
     // the host vectors die here: make the copies complete first
     return hip_status(hipStreamSynchronize(c->stream));
 }
@@ -305,6 +328,7 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     h.scratch_cpc = scratch_cpc((uint32_t)sz);
     h.error = c->error;
     h.tpart = d->geometry == TRMC_SLAB1D ? nullptr : reinterpret_cast<double*>(ws + L.tpart);
+    h.bsum = d->geometry == TRMC_SLAB1D ? nullptr : reinterpret_cast<double*>(ws + L.bsum);
     h.bigstate = d->geometry == TRMC_SLAB1D ? nullptr : ws + L.big;
 
     std::vector<double> eps(nc);
@@ -368,12 +392,17 @@ int launch_collide(trmc_ctx* c, int k)
         const CellRef* bigs = c->work[k][2];
         const uint32_t* pre = c->tile_prefix[k];
         const uint32_t tiles = c->n_tiles[k];
-        const size_t lds = sizeof(uint32_t) * 5 * c->lv_stride[k][2];
-        hipLaunchKernelGGL(k_tile_prep<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
-        hipLaunchKernelGGL(k_tile_dv<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
-        hipLaunchKernelGGL(k_big_tree<T>, dim3(nt), dim3(512), lds, c->stream, bigs, nt, c->lv_stride[k][2]);
-        hipLaunchKernelGGL(k_tile_gather<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
-        hipLaunchKernelGGL(k_big_collide<T>, dim3(nt), dim3(512), lds, c->stream, bigs, nt, c->lv_stride[k][2]);
+        const uint32_t stride = c->lv_stride[k][2];
+        const size_t lds1 = sizeof(uint32_t) * 5 * stride, lds8 = 8 * lds1;
+        const CellLists cl{c->cls_list[k], c->cls_count[k], c->max_cells};
+        const uint32_t wblocks = (nt + 7) / 8;
+        hipLaunchKernelGGL(k_tile_prep<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt, c->cls_count[k]);
+        hipLaunchKernelGGL(k_tile_bsum<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+        hipLaunchKernelGGL(k_big_split<T>, dim3(wblocks), dim3(512), lds8, c->stream, bigs, nt, stride, cl);
+        hipLaunchKernelGGL((k_big_tree<T, 64>), dim3(wblocks), dim3(512), lds8, c->stream, bigs, stride, cl);
+        hipLaunchKernelGGL((k_big_tree<T, 512>), dim3(nt), dim3(512), lds1, c->stream, bigs, stride, cl);
+        hipLaunchKernelGGL((k_big_collide<T, 64>), dim3(wblocks), dim3(512), lds8, c->stream, bigs, stride, cl);
+        hipLaunchKernelGGL((k_big_collide<T, 512>), dim3(nt), dim3(512), lds1, c->stream, bigs, stride, cl);
         hipLaunchKernelGGL(k_tile_zsum<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
         hipLaunchKernelGGL(k_tile_write<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
     }
@@ -461,6 +490,10 @@ int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trm
         }
         c->tile_prefix[k] = reinterpret_cast<uint32_t*>(c->ws + p);
         p += al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1));
+        c->cls_list[k] = reinterpret_cast<uint32_t*>(c->ws + p);
+        p += al(sizeof(uint32_t) * 2 * std::max(1u, max_cells));
+        c->cls_count[k] = reinterpret_cast<uint32_t*>(c->ws + p);
+        p += al(2 * sizeof(uint32_t));
     }
     c->inst_ptrs = reinterpret_cast<InstDev**>(c->ws + p);
     p += al(sizeof(InstDev*) * std::max(1u, max_instances));
@@ -503,26 +536,115 @@ int trmc_retire(trmc_ctx* c, uint32_t slot)
     return rebuild_tables(c);
 }
 
+namespace {
+
+// Every launch of one step on stream st: transport and sort of the slabs, the
+// collision step of each precision, the step counters.
+int enqueue_step(trmc_ctx* c, hipStream_t st)
+{
+    const hipStream_t keep = c->stream;
+    c->stream = st;
+    int rc = 0;
+    for (auto& s : c->slots) {
+        if (!s.active || s.host.geometry != GEOM_SLAB) continue;
+        rc = s.host.precision == PREC_FP64 ? launch_slab<double>(c, s) : launch_slab<float>(c, s);
+        if (rc) break;
+    }
+    for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_collide<float>(c, 0) : launch_collide<double>(c, 1);
+    if (!rc && c->n_active)
+        hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, st, c->inst_ptrs,
+                           c->n_active);
+    if (!rc && hipGetLastError() != hipSuccess) rc = TRMC_EIO;
+    c->stream = keep;
+    return rc;
+}
+
+void drop_graph(trmc_ctx* c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Capture one step on the context's private stream (the caller's stream may be
+// the null stream, which cannot be captured).
+int capture_step(trmc_ctx* c)
+{
+    if (c->graph_exec && hipStreamSynchronize(c->stream) != hipSuccess) return TRMC_EIO;
+    drop_graph(c);
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        return TRMC_EIO;
+    }
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TRMC_EIO;
+    const int rc = enqueue_step(c, c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : TRMC_EIO;
+    }
+    c->graph = g;
+    if (hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        c->graph_exec = nullptr;
+        drop_graph(c);
+        return TRMC_EIO;
+    }
+    c->graph_dirty = false;
+    return 0;
+}
+
+}  // namespace
+
 int trmc_step(trmc_ctx* c, uint32_t n_steps)
 {
     if (!c) return TRMC_EINVAL;
     if (c->sticky) return c->sticky;
+    if (n_steps == 0) return 0;
+    if (c->use_graph && c->graph_dirty) {
+        const int rc = capture_step(c);
+        if (rc) return c->sticky = rc;
+    }
     for (uint32_t it = 0; it < n_steps; ++it) {
-        for (auto& s : c->slots) {
-            if (!s.active || s.host.geometry != GEOM_SLAB) continue;
-            int rc = s.host.precision == PREC_FP64 ? launch_slab<double>(c, s) : launch_slab<float>(c, s);
+        if (c->use_graph) {
+            if (hipGraphLaunch(c->graph_exec, c->stream) != hipSuccess) return c->sticky = TRMC_EIO;
+        } else {
+            const int rc = enqueue_step(c, c->stream);
             if (rc) return c->sticky = rc;
         }
-        for (int k = 0; k < 2; ++k) {
-            int rc = k == 0 ? launch_collide<float>(c, 0) : launch_collide<double>(c, 1);
-            if (rc) return c->sticky = rc;
-        }
-        if (c->n_active)
-            hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, c->stream,
-                               c->inst_ptrs, c->n_active);
-        if (hipGetLastError() != hipSuccess) return c->sticky = TRMC_EIO;
         for (auto& s : c->slots)
             if (s.active) s.steps++;
+    }
+    return 0;
+}
+
+int trmc_set_schedule(trmc_ctx* c, const uint32_t* paths, uint32_t n_buckets)
+{
+    if (!c || (n_buckets && !paths) || n_buckets > TRMC_SCHED_BUCKETS) return TRMC_EINVAL;
+    for (uint32_t b = 0; b < n_buckets; ++b)
+        if (paths[b] > TRMC_PATH_TILED) return TRMC_EINVAL;
+    for (uint32_t b = 0; b < TRMC_SCHED_BUCKETS; ++b) c->sched[b] = b < n_buckets ? paths[b] : TRMC_PATH_DEFAULT;
+    return rebuild_tables(c);
+}
+
+int trmc_get_schedule(const trmc_ctx* c, uint32_t* paths, uint32_t n_buckets)
+{
+    if (!c || (n_buckets && !paths) || n_buckets > TRMC_SCHED_BUCKETS) return TRMC_EINVAL;
+    for (uint32_t b = 0; b < n_buckets; ++b) paths[b] = c->sched[b];
+    return 0;
+}
+
+int trmc_use_graph(trmc_ctx* c, int on)
+{
+    if (!c) return TRMC_EINVAL;
+    if (c->sticky) return c->sticky;
+    c->use_graph = on != 0;
+    if (!c->use_graph) {
+        // launches already enqueued keep the executable graph alive until they end
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return c->sticky = TRMC_EIO;
+        drop_graph(c);
+        c->graph_dirty = true;
     }
     return 0;
 }
@@ -635,6 +757,8 @@ int trmc_destroy(trmc_ctx* c)
 {
     if (!c) return TRMC_EINVAL;
     const hipError_t e = hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return e == hipSuccess ? 0 : TRMC_EIO;
 }

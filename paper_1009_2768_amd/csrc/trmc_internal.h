@@ -16,6 +16,7 @@ constexpr uint32_t kMaxSlabCells = 12288;  // LDS histogram of the sort
 constexpr uint32_t kSortTile = 4096;     // particles per tile of the counting sort
 constexpr uint32_t kTile = 8192;         // slots per tile of the tiled collision pipeline
 constexpr uint32_t kBigStateBytes = 1024; // per-cell state of the tiled pipeline (before its level arrays)
+constexpr uint32_t kRoleBlock = 512;     // roles per block sum of the tiled pipeline
 constexpr uint32_t kCollideThreads = 512;
 constexpr uint32_t kSmallPerBlock = kCollideThreads / 64;  // wave-per-cell groups per workgroup
 constexpr uint32_t kSmallCell = 4096;  // cells expected to hold at most this many particles use one wave
@@ -53,6 +54,7 @@ struct InstDev {
     uint64_t scratch_cpc;     // scratch bytes per cell
     uint32_t* error;          // context error word
     double* tpart;            // tiled pipeline: [ceil(n / kTile)][8] partial sums
+    double* bsum;             // tiled pipeline: [ceil(n / kRoleBlock)][8] sums over blocks of roles
     unsigned char* bigstate;  // tiled pipeline: state and level arrays between kernels
 };
 
