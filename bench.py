@@ -65,6 +65,40 @@ def build_context(T, N, eps, alpha, init, seed, precision, device="cuda"):
     return ctx, (vx, vy, vz)
 
 
+def source_sha256() -> str:
+    """Hash of the kernel sources (names and contents), to tell whether stored
+    HBM counter figures still describe the kernels being timed."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1009_2768_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, table):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or None when the
+    kernel sources or the schedule differ from those the counters were taken with."""
+    path = os.path.join(ROOT, "profiles", "k_collide_batched_homogeneous_4096.traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_sha256() or kernel not in rec.get("kernel", ""):
+        return None
+    names = ["default", "group", "wave", "tiled"]
+    want = [0] * 32
+    for item in rec.get("table", "").split(","):
+        if item:
+            b, name = item.split(":")
+            want[int(b)] = names.index(name)
+    return rec["bytes_per_launch"] if list(table) == want else None
+
+
 def cpu_baseline(N, eps, alpha, init, seed, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same batch (every 64th instance,
     one step each, stopping once the time budget is spent)."""
@@ -176,6 +210,9 @@ def main():
     algo_bytes = 6 * sz * total  # one read and one write of (vx, vy, vz) per particle-step
     avg_ms = float(np.mean(step_ms))
     achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
+    kernel = "k_collide<float>" if prec == T.FP32_MIXED else "k_collide<double>"
+    tiled = any(table[T.size_bucket(i)] in (0, 3) for i in ctx.instances)
+    traffic = None if tiled else stored_traffic(kernel, table)
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, kernel events {avg_ms:.3f} ms")
     line = {
         "metric": "particle-collision-step updates/sec",
@@ -196,8 +233,9 @@ def main():
                    "instances": args.instances, "particles": total, "precision": args.precision,
                    "schedule": schedule, "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_collide<float> (+ k_advance, about 2 us)"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": (kernel + " (+ k_advance, about 4 us)") if not tiled else
+                     "tile pipeline + " + kernel + " (several kernels per step)"},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
