@@ -49,7 +49,9 @@ __device__ __forceinline__ void gsync_lds()
 }
 
 // Sum over the group; every thread receives the total.  Fixed order: butterfly
-// inside each wave, then the waves in order.  `red` holds (G/64) * K doubles.
+// inside each wave, then the waves in order.  `red` holds (G/64 + 1) * K
+// doubles.  Thread k sums component k over the waves and every thread reads
+// the K totals: each thread holds K doubles, not K per wave.
 template <int G, int K>
 __device__ __forceinline__ void gsum(double (&v)[K], double* red)
 {
@@ -61,19 +63,23 @@ __device__ __forceinline__ void gsum(double (&v)[K], double* red)
         v[k] = a;
     }
     if constexpr (G > 64) {
-        const int lane = threadIdx.x & 63, wave = (threadIdx.x % G) >> 6;
+        constexpr int NW = G / 64;
+        const int tid = threadIdx.x % G, lane = tid & 63, wave = tid >> 6;
         gsync_lds<G>();
         if (lane == 0) {
 #pragma unroll
             for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
         }
         gsync_lds<G>();
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
+        if (tid < K) {
             double a = 0.0;
-            for (int w = 0; w < G / 64; ++w) a += red[w * K + k];
-            v[k] = a;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) a += red[w * K + tid];
+            red[NW * K + tid] = a;
         }
+        gsync_lds<G>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = red[NW * K + k];
     }
 }
 
@@ -269,7 +275,8 @@ struct CellMem {
     {
         cap = coll_cap(n);
         ocap = 2ull * cap;
-        unsigned char* base = I->scratch + I->scratch_bpp * (uint64_t)off + I->scratch_cpc * (uint64_t)cell;
+        // the cell is the same on every lane of the wave: scalar base pointers
+        unsigned char* base = uni(I->scratch + I->scratch_bpp * (uint64_t)off + I->scratch_cpc * (uint64_t)cell);
         role = reinterpret_cast<uint32_t*>(base);
         base += align16(4ull * n);
         leaf = reinterpret_cast<T*>(base);
@@ -389,14 +396,14 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
     const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64u - lane));
     unsigned long long ncoll = 0;
     for (;;) {
-        const uint32_t me = sh.me;
+        const uint32_t me = uni(sh.me);
         for (uint32_t l = tid; l <= me; l += G) L.run[l] = 0;
         gsync_lds<G>();
         ncoll = 0;
         bool ovf = false;
         for (uint32_t l = me; l >= 1; --l) {
-            const uint32_t Rl = L.run[l];
-            const uint32_t odd = Rl & 1u, Nl = L.N[l];
+            const uint32_t Rl = uni(L.run[l]);
+            const uint32_t odd = Rl & 1u, Nl = uni(L.N[l]);
             const uint32_t own = Nl > odd ? (Nl - odd + 1u) / 2u : 0u;
             const uint32_t Cl = (Rl + 1u) / 2u + own;
             if (tid == 0) {
@@ -612,16 +619,16 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const Leve
 {
     const uint4 pk = draw(key, 0, TAG_PERM, 0);
     const uint32_t half = perm_half(n);
-    const uint32_t N0 = sh.N0, P = n - N0, me = sh.me;
+    const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
     const uint64_t ocap = M.ocap;
     unsigned long long above = ncoll;  // collisions of deeper levels precede level l's
     uint32_t fp = 0;                   // finals of shallower levels
     for (uint32_t l = 1; l <= me; ++l) {
-        const uint32_t Cl = L.C[l], Rl = L.Rtot[l];
+        const uint32_t Cl = uni(L.C[l]), Rl = uni(L.Rtot[l]);
         if (Cl == 0) continue;
         above -= Cl;
         const uint32_t fst = (uint32_t)above;
-        const uint32_t oo = L.outoff[l];
+        const uint32_t oo = uni(L.outoff[l]);
         for (uint32_t c = tid; c < Cl; c += G) {
             const uint32_t id = fst + c;
             const uint32_t j = M.jarr[id], h = l - 1u - j;

@@ -67,22 +67,23 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     extern __shared__ uint32_t lds_levels[];
     __shared__ GroupLds<G> glds[NGRP];
 
-    const uint32_t grp = threadIdx.x / G;
+    const uint32_t grp = uni((uint32_t)(threadIdx.x / G));
     const uint32_t wi = blk * NGRP + grp;
     if (wi >= n_work) return;  // whole group leaves together
     GroupLds<G>& gl = glds[grp];
     CellShared& sh = gl.sh;
     const uint32_t tid = threadIdx.x % G;
-    InstDev* __restrict__ I = work[wi].inst;
-    const uint32_t cell = work[wi].cell;
-    const uint32_t off = I->cell_off[cell];
-    const uint32_t n = I->cell_off[cell + 1] - off;
-    const uint32_t buf = (I->geometry == GEOM_SLAB) ? (I->cur ^ 1u) : 0u;
-    T* __restrict__ vx = reinterpret_cast<T*>(I->vx[buf]) + off;
-    T* __restrict__ vy = reinterpret_cast<T*>(I->vy[buf]) + off;
-    T* __restrict__ vz = reinterpret_cast<T*>(I->vz[buf]) + off;
+    // everything about the cell is wave-uniform: keep it in scalar registers
+    InstDev* __restrict__ I = uni(work[wi].inst);
+    const uint32_t cell = uni(work[wi].cell);
+    const uint32_t off = uni(I->cell_off[cell]);
+    const uint32_t n = uni(I->cell_off[cell + 1]) - off;
+    const uint32_t buf = (uni(I->geometry) == GEOM_SLAB) ? (uni(I->cur) ^ 1u) : 0u;
+    T* __restrict__ vx = uni(reinterpret_cast<T*>(I->vx[buf]) + off);
+    T* __restrict__ vy = uni(reinterpret_cast<T*>(I->vy[buf]) + off);
+    T* __restrict__ vz = uni(reinterpret_cast<T*>(I->vz[buf]) + off);
     CellStats* st = I->stats + cell;
-    const Key key{I->seed, I->uid, cell, I->step};
+    const Key key = uni(Key{I->seed, I->uid, cell, I->step});
 
     if (n < 2) {
         if (tid == 0) {
@@ -317,14 +318,39 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
 // Cells of the workgroup-per-cell list occupy the first n_big workgroups, cells
 // of the wave-per-cell list (eight per workgroup) the rest.
 template <typename T>
-__global__ __launch_bounds__(kCollideThreads) void k_collide(const CellRef* __restrict__ big, uint32_t n_big,
-                                                             uint32_t lv_big, const CellRef* __restrict__ small,
-                                                             uint32_t n_small, uint32_t lv_small)
+__device__ __forceinline__ void collide_entry(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big,
+                                              const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small)
 {
     if (blockIdx.x < n_big)
         collide_cells<T, kCollideThreads, kCollideThreads>(big, n_big, blockIdx.x, lv_big);
     else
         collide_cells<T, kCollideThreads, 64>(small, n_small, blockIdx.x - n_big, lv_small);
+}
+
+// The per-cell chains are latency bound, so resident waves matter: the FP32
+// kernel is held to TRMC_F32_WAVES_PER_EU waves per SIMD (its natural register count
+// is a few registers above that bound; the spill is a few dwords).
+#ifndef TRMC_F32_WAVES_PER_EU
+#define TRMC_F32_WAVES_PER_EU 6
+#endif
+template <typename T>
+__global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
+
+template <>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(TRMC_F32_WAVES_PER_EU, 8))) void
+k_collide<float>(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big, const CellRef* __restrict__ small,
+                 uint32_t n_small, uint32_t lv_small)
+{
+    collide_entry<float>(big, n_big, lv_big, small, n_small, lv_small);
+}
+
+template <>
+__global__ __launch_bounds__(kCollideThreads) void k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,
+                                                                     uint32_t lv_big,
+                                                                     const CellRef* __restrict__ small,
+                                                                     uint32_t n_small, uint32_t lv_small)
+{
+    collide_entry<double>(big, n_big, lv_big, small, n_small, lv_small);
 }
 
 #ifdef TRMC_PHASE_TIMING
@@ -339,7 +365,6 @@ extern "C" int trmc_debug_phase_totals(unsigned long long* out /* 48 */, int res
 }
 #endif
 
-template __global__ void k_collide<float>(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
-template __global__ void k_collide<double>(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
+
 
 }  // namespace trmc

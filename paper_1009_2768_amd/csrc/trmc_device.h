@@ -19,6 +19,23 @@ struct Key {
     uint32_t seed, uid, cell, step;
 };
 
+// Values equal on every lane of a wave, moved to scalar registers (the first
+// active lane's copy): cell indices, sizes, keys and base pointers.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(v))); }
+template <typename P>
+__device__ __forceinline__ P* uni(P* p)
+{
+    return reinterpret_cast<P*>(uni((uint64_t)reinterpret_cast<uintptr_t>(p)));
+}
+__device__ __forceinline__ Key uni(const Key& k) { return Key{uni(k.seed), uni(k.uid), uni(k.cell), uni(k.step)}; }
+
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                           uint32_t k1)
 {
@@ -67,7 +84,7 @@ __device__ __forceinline__ uint32_t tree_choice(const Key& k, uint32_t l, uint32
 // two-part ln 2, degree-13 Taylor polynomial by Horner, scaling by 2^k), with
 // contraction off, so that q = exp(-mu dt/eps) has reproducible bits.
 // ---------------------------------------------------------------------------
-__device__ __noinline__ double exp_neg(double x)
+__device__ __forceinline__ double exp_neg(double x)
 {
 #pragma clang fp contract(off)
     const double head = 0x1.62e42p-1;
@@ -105,7 +122,7 @@ __device__ __forceinline__ double grid_up20(double g)
 }
 
 // Iround of Alg. 4.2 (floor(y) + 1 with probability frac(y)), contraction off.
-__device__ __noinline__ uint32_t iround_prod(double q, uint32_t rem, double u)
+__device__ __forceinline__ uint32_t iround_prod(double q, uint32_t rem, double u)
 {
 #pragma clang fp contract(off)
     const double y = q * (double)rem;
