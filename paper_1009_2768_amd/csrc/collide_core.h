@@ -263,9 +263,10 @@ struct GroupLds {
 // Pointers into one cell's scratch region (layout in trmc_internal.h).
 template <typename T>
 struct CellMem {
-    uint32_t* role;  // [n] role index of each slot
-    T* leaf;         // [3][n] leaves by leaf rank
-    T* fin;          // [3][n] finals by destination slot
+    uint32_t* role;  // [n] role index of each slot (inverse of the keyed permutation)
+    uint32_t* fwd;   // [n] slot of each role index (the permutation itself; tile path)
+    T* leaf;         // [3][n] leaves by leaf rank (whole-cell path)
+    T* fin;          // [3][n] finals by leaf rank (final r goes to the slot of leaf r)
     uint32_t* jarr;  // [cap] sub-level choice of each collision
     uint32_t* rA;    // [cap] rank of request A at level j
     uint32_t* rB;    // [cap] rank of request B at level l-1-j
@@ -278,6 +279,8 @@ struct CellMem {
         // the cell is the same on every lane of the wave: scalar base pointers
         unsigned char* base = uni(I->scratch + I->scratch_bpp * (uint64_t)off + I->scratch_cpc * (uint64_t)cell);
         role = reinterpret_cast<uint32_t*>(base);
+        base += align16(4ull * n);
+        fwd = reinterpret_cast<uint32_t*>(base);
         base += align16(4ull * n);
         leaf = reinterpret_cast<T*>(base);
         base += 3 * align16(sizeof(T) * (uint64_t)n);
@@ -558,14 +561,30 @@ __device__ __forceinline__ bool level_offsets(uint32_t n, unsigned long long nco
     return sh.overflow == 0u;
 }
 
-// Leaves and sums of the unchanged and thermalized sets over slots
-// [s_begin, s_end) of a cell with NT threads (this thread's share): sums =
-// {kept (vx-m)^2, thermalized (vx-m)^2, thermalized v-m (3), thermalized |v-m|^2}.
+// Leaf rank of role index i in the leaf range [kept_end, leaf_end): roles N0,
+// N0 + 1, ... are leaves 0, 1, ...; borrowed roles N0 - 1, N0 - 2, ... follow
+// as leaves P, P + 1, ... (P = n - N0).
+__device__ __forceinline__ uint32_t leaf_rank(uint32_t i, uint32_t N0, uint32_t P)
+{
+    return i >= N0 ? i - N0 : P + (N0 - 1u - i);
+}
+
+// Role index of leaf r (inverse of leaf_rank).
+__device__ __forceinline__ uint32_t leaf_role(uint32_t r, uint32_t N0, uint32_t P)
+{
+    return r < P ? N0 + r : N0 - 1u - (r - P);
+}
+
+// Leaves and sums of the unchanged and thermalized sets over slots [s_begin,
+// s_end) of a cell with NT threads (this thread's share): leaf r is copied to
+// leaf[r]; sums = {kept (vx-m)^2, thermalized (vx-m)^2, thermalized v-m (3),
+// thermalized |v-m|^2}.  Roles below kept_end are unchanged, roles from
+// leaf_end on are thermalized, the others are leaves.
 template <typename T, int NT>
-__device__ __forceinline__ void gather_range(const T* vx, const T* vy, const T* vz, const uint32_t* role, T* leaf,
-                                             uint32_t n, uint32_t s_begin, uint32_t s_end, uint32_t N0,
-                                             uint32_t kept_end, uint32_t leaf_end, double mx, double my, double mz,
-                                             uint32_t tid, double (&sums)[6])
+__device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* vz, const uint32_t* role, T* leaf,
+                                            uint32_t n, uint32_t N0, uint32_t s_begin, uint32_t s_end,
+                                            uint32_t kept_end, uint32_t leaf_end, double mx, double my, double mz,
+                                            uint32_t tid, double (&sums)[6])
 {
     constexpr int U = 4;
     const uint32_t P = n - N0;
@@ -589,7 +608,7 @@ __device__ __forceinline__ void gather_range(const T* vx, const T* vy, const T* 
                 const double d = (double)ax[u] - mx;
                 sums[0] += d * d;
             } else if (i < leaf_end) {
-                const uint32_t r = (i < N0) ? P + (N0 - 1u - i) : i - N0;
+                const uint32_t r = leaf_rank(i, N0, P);
                 leaf[r] = ax[u];
                 leaf[n + r] = ay[u];
                 leaf[2 * n + r] = az[u];
@@ -606,19 +625,22 @@ __device__ __forceinline__ void gather_range(const T* vx, const T* vy, const T* 
 }
 
 // d. Collisions, shallowest level first; all collisions of a level in parallel
-//    (eq. Maxwell_coll-r, eq. n3d-r; Alg. 4.4 acceptance).  Final r goes to the
-//    slot of leaf r.  Per-thread counters and the finals' sum of (vx-m)^2.
-//    Leaves come from M.leaf, indexed by leaf rank (ByRole = false, gathered by
-//    the whole-cell kernel) or by role index (ByRole = true: M.leaf is then the
-//    cell's role-ordered copy, leaf r being role N0 + r, or N0 - 1 - (r - P)
-//    for a borrowed one).
-template <typename T, int G, bool ByRole>
-__device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const Levels& L, const CellShared& sh,
-                                          const CellMem<T>& M, unsigned long long ncoll, T alpha, T gT, double mx,
-                                          uint32_t tid, uint32_t& dummies, uint32_t& viol, double& sfin)
+//    (eq. Maxwell_coll-r, eq. n3d-r; Alg. 4.4 acceptance).  Leaf r is read
+//    from leaf[r] (gathered before), or with FromSlots from its slot
+//    fwd[leaf_role(r)] of the pre-step velocities (vx, vy, vz); final r is
+//    stored at fin[r] (the write-back puts it in the slot of leaf r).
+//    Per-thread counters and the finals' sum of (vx-m)^2.
+#ifndef TRMC_BOTTOM_UP_BATCH
+#define TRMC_BOTTOM_UP_BATCH 2
+#endif
+constexpr int kBU = TRMC_BOTTOM_UP_BATCH;  // collisions per thread per batch in bottom_up
+
+template <typename T, int G, bool FromSlots>
+__device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const T* vx, const T* vy, const T* vz,
+                                          const Levels& L, const CellShared& sh, const CellMem<T>& M,
+                                          unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
+                                          uint32_t& dummies, uint32_t& viol, double& sfin)
 {
-    const uint4 pk = draw(key, 0, TAG_PERM, 0);
-    const uint32_t half = perm_half(n);
     const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
     const uint64_t ocap = M.ocap;
     unsigned long long above = ncoll;  // collisions of deeper levels precede level l's
@@ -629,45 +651,63 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const Leve
         above -= Cl;
         const uint32_t fst = (uint32_t)above;
         const uint32_t oo = uni(L.outoff[l]);
-        for (uint32_t c = tid; c < Cl; c += G) {
-            const uint32_t id = fst + c;
-            const uint32_t j = M.jarr[id], h = l - 1u - j;
-            const uint32_t ra = M.rA[id], rb = M.rB[id];
-            Vec3<T> a, b;
-            if (j == 0) {
-                const uint32_t q = ByRole ? (ra < P ? N0 + ra : N0 - 1u - (ra - P)) : ra;
-                a = Vec3<T>{M.leaf[q], M.leaf[n + q], M.leaf[2 * n + q]};
-            } else {
-                const uint64_t p = (uint64_t)L.outoff[j] + ra;
-                a = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
-            }
-            if (h == 0) {
-                const uint32_t q = ByRole ? (rb < P ? N0 + rb : N0 - 1u - (rb - P)) : rb;
-                b = Vec3<T>{M.leaf[q], M.leaf[n + q], M.leaf[2 * n + q]};
-            } else {
-                const uint64_t p = (uint64_t)L.outoff[h] + rb;
-                b = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
-            }
-            T xi1, xi2, xacc;
-            Draws<T>::coll(key, l, c, xi1, xi2, xacc);
-            Vec3<T> out[2];
-            if (!collide<T>(a, b, xi1, xi2, xacc, alpha, gT, out[0], out[1], viol)) dummies++;
+        // kBU collisions per thread: every index and input load of the batch
+        // is issued before the first collision is computed
+        for (uint32_t c0 = tid; c0 < Cl; c0 += G * kBU) {
+            Vec3<T> a[kBU], b[kBU];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const uint32_t o = 2u * c + (uint32_t)k;
-                if (o < Rl) {
-                    const uint64_t p = (uint64_t)oo + o;
-                    M.outv[p] = out[k].x;
-                    M.outv[ocap + p] = out[k].y;
-                    M.outv[2 * ocap + p] = out[k].z;
+            for (int k = 0; k < kBU; ++k) {
+                const uint32_t c = c0 + (uint32_t)k * G;
+                const uint32_t id = fst + (c < Cl ? c : 0u);  // collision 0 stands in past the end
+                const uint32_t j = M.jarr[id], h = l - 1u - j;
+                const uint32_t ra = M.rA[id], rb = M.rB[id];
+                if (j == 0) {
+                    if constexpr (FromSlots) {
+                        const uint32_t sl = M.fwd[leaf_role(ra, N0, P)];
+                        a[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
+                    } else {
+                        a[k] = Vec3<T>{M.leaf[ra], M.leaf[n + ra], M.leaf[2 * n + ra]};
+                    }
                 } else {
-                    const uint32_t r = fp + (o - Rl);
-                    const uint32_t fs = perm_forward(r < P ? N0 + r : N0 - 1u - (r - P), n, half, pk);
-                    M.fin[fs] = out[k].x;
-                    M.fin[n + fs] = out[k].y;
-                    M.fin[2 * n + fs] = out[k].z;
-                    const double d = (double)out[k].x - mx;
-                    sfin += d * d;
+                    const uint64_t p = (uint64_t)L.outoff[j] + ra;
+                    a[k] = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
+                }
+                if (h == 0) {
+                    if constexpr (FromSlots) {
+                        const uint32_t sl = M.fwd[leaf_role(rb, N0, P)];
+                        b[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
+                    } else {
+                        b[k] = Vec3<T>{M.leaf[rb], M.leaf[n + rb], M.leaf[2 * n + rb]};
+                    }
+                } else {
+                    const uint64_t p = (uint64_t)L.outoff[h] + rb;
+                    b[k] = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kBU; ++k) {
+                const uint32_t c = c0 + (uint32_t)k * G;
+                if (c >= Cl) break;
+                T xi1, xi2, xacc;
+                Draws<T>::coll(key, l, c, xi1, xi2, xacc);
+                Vec3<T> out[2];
+                if (!collide<T>(a[k], b[k], xi1, xi2, xacc, alpha, gT, out[0], out[1], viol)) dummies++;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const uint32_t o = 2u * c + (uint32_t)e;
+                    if (o < Rl) {
+                        const uint64_t p = (uint64_t)oo + o;
+                        M.outv[p] = out[e].x;
+                        M.outv[ocap + p] = out[e].y;
+                        M.outv[2 * ocap + p] = out[e].z;
+                    } else {
+                        const uint32_t r = fp + (o - Rl);
+                        M.fin[r] = out[e].x;
+                        M.fin[n + r] = out[e].y;
+                        M.fin[2 * n + r] = out[e].z;
+                        const double d = (double)out[e].x - mx;
+                        sfin += d * d;
+                    }
                 }
             }
         }
@@ -721,19 +761,21 @@ __device__ __forceinline__ void decide(InstDev* I, uint32_t cell, uint32_t n, co
     sh.decision = decision;
 }
 
-// Sums over the roles [lo, hi) of a cell from its role-ordered copy vr (3 x n)
-// and its block sums bs (kRoleBlock roles per block, 8 doubles each: sum of
-// v - m (3), of (vx - m)^2, of |v - m|^2), with the cell mean m: whole blocks
-// from bs, the partial blocks at both ends from vr.  This thread's share in
-// out[5]; the caller reduces over the group.
+// Sums over the roles [lo, hi) of a cell, centred on the cell mean m: whole
+// blocks of kRoleBlock roles from the block sums bs (8 doubles each: sum of
+// v - m (3), of (vx - m)^2, of |v - m|^2), the partial blocks at both ends from
+// the slots fwd[i] of the velocities.  This thread's share in out[5]; the
+// caller reduces over the group.
 template <typename T, int G>
-__device__ __forceinline__ void range_sums(const T* vr, const double* bs, uint32_t n, uint32_t lo, uint32_t hi,
-                                           double mx, double my, double mz, uint32_t tid, double (&out)[5])
+__device__ __forceinline__ void range_sums(const T* vx, const T* vy, const T* vz, const uint32_t* fwd,
+                                           const double* bs, uint32_t lo, uint32_t hi, double mx, double my,
+                                           double mz, uint32_t tid, double (&out)[5])
 {
     if (lo >= hi) return;
     const uint32_t b_lo = (lo + kRoleBlock - 1) / kRoleBlock, b_hi = hi / kRoleBlock;
     auto add_one = [&](uint32_t i) {
-        const double dx = (double)vr[i] - mx, dy = (double)vr[n + i] - my, dz = (double)vr[2 * n + i] - mz;
+        const uint32_t sl = fwd[i];
+        const double dx = (double)vx[sl] - mx, dy = (double)vy[sl] - my, dz = (double)vz[sl] - mz;
         out[0] += dx;
         out[1] += dy;
         out[2] += dz;
@@ -756,16 +798,17 @@ __device__ __forceinline__ void range_sums(const T* vr, const double* bs, uint32
     }
 }
 
-// Sums of an attempt from the role-ordered copy: all = {kept (vx-m)^2, th
-// (vx-m)^2, th v-m (3), th |v-m|^2, (finals, filled by the caller)}.
+// Sums of an attempt: all = {kept (vx-m)^2, th (vx-m)^2, th v-m (3), th
+// |v-m|^2, (finals, filled by the caller)}.
 template <typename T, int G>
-__device__ __forceinline__ void attempt_sums(const T* vr, const double* bs, uint32_t n, uint32_t kept_end,
-                                             uint32_t leaf_end, double mx, double my, double mz, uint32_t tid,
-                                             double* red, double (&all)[7])
+__device__ __forceinline__ void attempt_sums(const T* vx, const T* vy, const T* vz, const uint32_t* fwd,
+                                             const double* bs, uint32_t n, uint32_t kept_end, uint32_t leaf_end,
+                                             double mx, double my, double mz, uint32_t tid, double* red,
+                                             double (&all)[7])
 {
     double k5[5] = {0, 0, 0, 0, 0}, t5[5] = {0, 0, 0, 0, 0};
-    range_sums<T, G>(vr, bs, n, 0u, kept_end, mx, my, mz, tid, k5);
-    range_sums<T, G>(vr, bs, n, leaf_end, n, mx, my, mz, tid, t5);
+    range_sums<T, G>(vx, vy, vz, fwd, bs, 0u, kept_end, mx, my, mz, tid, k5);
+    range_sums<T, G>(vx, vy, vz, fwd, bs, leaf_end, n, mx, my, mz, tid, t5);
     double v[6] = {k5[3], t5[3], t5[0], t5[1], t5[2], t5[4]};
     gsum<G, 6>(v, red);
     for (int q = 0; q < 6; ++q) all[q] = v[q];

@@ -25,6 +25,7 @@ namespace trmc {
 #ifdef TRMC_PHASE_TIMING
 // Profiling build only: per-phase wall-clock totals by cell-size class.
 __device__ unsigned long long g_phase[4][12];
+__device__ unsigned long long g_maxcell[12];
 #define TRMC_PHASE_BEGIN() unsigned long long ph_t = wall_clock64(), ph_acc[10] = {0,0,0,0,0,0,0,0,0,0}
 #define TRMC_PHASE(k)                                   \
     do {                                                \
@@ -42,7 +43,14 @@ __device__ unsigned long long g_phase[4][12];
                 tot += ph_acc[k];                                                 \
             }                                                                     \
             atomicAdd(&g_phase[cls][10], 1ull);                                   \
-            atomicMax(&g_phase[3][cls], tot);                                     \
+            const unsigned long long prev = atomicMax(&g_phase[3][cls], tot);     \
+            if (tot > prev && cls == 2) {                                         \
+                for (int k = 0; k < 8; ++k) g_maxcell[k] = ph_acc[k];             \
+                g_maxcell[8] = (nn);                                              \
+                g_maxcell[9] = sh.attempts;                                       \
+                g_maxcell[10] = sh.m;                                             \
+                g_maxcell[11] = sh.me;                                            \
+            }                                                                     \
         }                                                                         \
     } while (0)
 #else
@@ -151,13 +159,24 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const double dxm = s[0] * inv;
         const double mx = c0 + dxm, my = s[1] * inv, mz = s[2] * inv;
         double dmax = 0.0;
-        if (I->alpha != 0.0) {
+        if (uni((uint64_t)__double_as_longlong(I->alpha)) != 0ull) {
+            // two batches of loads in flight: the next batch is issued before
+            // the current one is reduced
             double d2max = 0.0;
+            T ax2[kUnroll], ay2[kUnroll], az2[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t i = tid + u * G;
+                const bool ok = i < n;
+                ax2[u] = ok ? vx[i] : T(0);
+                ay2[u] = ok ? vy[i] : T(0);
+                az2[u] = ok ? vz[i] : T(0);
+            }
             for (uint32_t s0 = tid; s0 < n; s0 += G * kUnroll) {
                 T bx[kUnroll], by[kUnroll], bz[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t i = s0 + u * G;
+                    const uint32_t i = s0 + G * kUnroll + u * G;
                     const bool ok = i < n;
                     bx[u] = ok ? vx[i] : T(0);
                     by[u] = ok ? vy[i] : T(0);
@@ -166,10 +185,16 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
                     if (s0 + u * G < n) {
-                        const double dx = (double)bx[u] - mx, dy = (double)by[u] - my, dz = (double)bz[u] - mz;
+                        const double dx = (double)ax2[u] - mx, dy = (double)ay2[u] - my, dz = (double)az2[u] - mz;
                         const double d2 = dx * dx + dy * dy + dz * dz;
                         d2max = d2 > d2max ? d2 : d2max;
                     }
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    ax2[u] = bx[u];
+                    ay2[u] = by[u];
+                    az2[u] = bz[u];
                 }
             }
             dmax = gmax<G>(d2max, gl.red);
@@ -202,13 +227,13 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
         const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
         double sums[6] = {0, 0, 0, 0, 0, 0};
-        gather_range<T, G>(vx, vy, vz, M.role, M.leaf, n, 0u, n, N0, kept_end, leaf_end, mx, my, mz, tid, sums);
+        gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, mx, my, mz, tid, sums);
         gsync<G>();  // leaves visible
         TRMC_PHASE(3);
 
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
-        bottom_up<T, G, false>(key, n, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
+        bottom_up<T, G, false>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
         TRMC_PHASE(4);
 
         double all[7] = {sums[0], sums[1], sums[2], sums[3], sums[4], sums[5], sfin};
@@ -286,26 +311,43 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const double a = sh.a_th;
         const double u0 = sh.ur[0], u1 = sh.ur[1], u2 = sh.ur[2];
         const double z0 = sh.zbar[0], z1 = sh.zbar[1], z2 = sh.zbar[2];
-        for (uint32_t s0 = tid; s0 < n; s0 += G * kUnroll) {
-            uint32_t ro[kUnroll];
+        constexpr int kWU = 2;
+        // loads of a batch are issued before any is used: the roles and current
+        // values, then the finals of the leaf slots (final r of leaf r)
+        for (uint32_t s0 = tid; s0 < n; s0 += G * kWU) {
+            uint32_t ro[kWU];
+            T fx[kWU], fy[kWU], fz[kWU], cx[kWU], cy[kWU], cz[kWU];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t i = s0 + u * G;
-                ro[u] = i < n ? M.role[i] : 0u;
+            for (int u = 0; u < kWU; ++u) {
+                const uint32_t s = s0 + u * G;
+                const bool ok = s < n;
+                ro[u] = ok ? M.role[s] : 0u;
+                cx[u] = ok ? vx[s] : T(0);
+                cy[u] = ok ? vy[s] : T(0);
+                cz[u] = ok ? vz[s] : T(0);
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kWU; ++u) {
+                const uint32_t i = ro[u];
+                const bool lf = s0 + u * G < n && i >= kept_end && i < leaf_end;
+                const uint32_t r = lf ? leaf_rank(i, N0, P) : 0u;
+                fx[u] = lf ? M.fin[r] : T(0);
+                fy[u] = lf ? M.fin[n + r] : T(0);
+                fz[u] = lf ? M.fin[2 * n + r] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kWU; ++u) {
                 const uint32_t s = s0 + u * G;
                 const uint32_t i = ro[u];
                 if (s >= n || i < kept_end) continue;
                 if (i < leaf_end) {
-                    vx[s] = M.fin[s];
-                    vy[s] = M.fin[n + s];
-                    vz[s] = M.fin[2 * n + s];
+                    vx[s] = fx[u];
+                    vy[s] = fy[u];
+                    vz[s] = fz[u];
                 } else if (thermalize) {
-                    vx[s] = (T)(u0 + a * ((double)vx[s] - z0));
-                    vy[s] = (T)(u1 + a * ((double)vy[s] - z1));
-                    vz[s] = (T)(u2 + a * ((double)vz[s] - z2));
+                    vx[s] = (T)(u0 + a * ((double)cx[u] - z0));
+                    vy[s] = (T)(u1 + a * ((double)cy[u] - z1));
+                    vz[s] = (T)(u2 + a * ((double)cz[u] - z2));
                 }
             }
         }
@@ -354,9 +396,10 @@ __global__ __launch_bounds__(kCollideThreads) void k_collide<double>(const CellR
 }
 
 #ifdef TRMC_PHASE_TIMING
-extern "C" int trmc_debug_phase_totals(unsigned long long* out /* 48 */, int reset)
+extern "C" int trmc_debug_phase_totals(unsigned long long* out /* 60 */, int reset)
 {
     if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return -5;
+    if (hipMemcpyFromSymbol(out + 48, HIP_SYMBOL(g_maxcell), sizeof(g_maxcell)) != hipSuccess) return -5;
     if (reset) {
         static const unsigned long long zero[4][12] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), zero, sizeof(zero)) != hipSuccess) return -5;

@@ -3,14 +3,14 @@
 // loads in flight) around per-cell kernels for the parts that need the whole
 // cell (the trees and the collisions):
 //
-//   k_tile_prep    tiles: role of every slot (keyed permutation), the cell's
-//                  role-ordered copy, partial sums for the mean
+//   k_tile_prep    tiles: role of every slot and slot of every role (keyed
+//                  permutation and its inverse), partial sums for the mean
 //   k_tile_bsum    tiles: sums over blocks of roles; max |v - mean|^2 (VHS majorant)
 //   k_big_split    cells: moments, tau, split (Alg. 4.2); light / heavy lists
 //   k_big_tree     cells: collision trees (Alg. 4.3)
 //   k_big_collide  cells: sums of the unchanged / thermalized sets from block
-//                  sums, collisions level by level (leaves read from the
-//                  role-ordered copy), adaptive test (Sec. 4.3); a rejected
+//                  sums, collisions level by level (leaves read through the
+//                  slot of each role), adaptive test (Sec. 4.3); a rejected
 //                  attempt is redone inside
 //   k_tile_zsum    tiles: sums of the Maxwellian normals of the thermalized set
 //   k_tile_write   tiles: leaves take the finals, thermalized slots the rescaled
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
     CellMem<T> M;
     M.init(V.I, 0, 0, n);
     uint32_t* role = M.role;
-    T* vr = M.leaf;  // role-ordered copy of the cell
+    uint32_t* fwd = M.fwd;
     const double c0 = (double)V.vx[0];
     constexpr int U = 4;
     double s[4] = {0, 0, 0, 0};
@@ -121,9 +121,7 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
                 s[3] += dx * dx;
                 const uint32_t r = perm_inverse(i, n, half, pk);
                 role[i] = r;
-                vr[r] = ax[u];
-                vr[n + r] = ay[u];
-                vr[2 * n + r] = az[u];
+                fwd[r] = i;
             }
         }
 #pragma unroll
@@ -165,7 +163,7 @@ __device__ __forceinline__ void cell_mean(const InstDev* I, uint32_t n, double c
     Sn = sn > 0.0 ? sn : 0.0;
 }
 
-// Sums over blocks of kRoleBlock roles of the role-ordered copy, centred on the
+// Sums over blocks of kRoleBlock roles (each role read from its slot), centred on the
 // cell mean (sum of v - m, of (vx - m)^2, of |v - m|^2), and for VHS the tile's
 // max |v - m|^2.  Any role range's sums are then a few block sums plus two
 // partial blocks (range_sums), so the attempts of the adaptive test cost
@@ -188,14 +186,15 @@ __global__ __launch_bounds__(kTT) void k_tile_bsum(const CellRef* __restrict__ b
     const double mx = mean[0], my = mean[1], mz = mean[2];
     CellMem<T> M;
     M.init(V.I, 0, 0, n);
-    const T* vr = M.leaf;
+    const uint32_t* fwd = M.fwd;
     const uint32_t r_begin = k * kTile, r_end = (r_begin + kTile < n) ? r_begin + kTile : n;
     double d2max = 0.0;
     for (uint32_t b0 = r_begin; b0 < r_end; b0 += kRoleBlock) {
         const uint32_t b1 = (b0 + kRoleBlock < r_end) ? b0 + kRoleBlock : r_end;
         double sv[5] = {0, 0, 0, 0, 0};
         for (uint32_t i = b0 + threadIdx.x; i < b1; i += kTT) {
-            const double dx = (double)vr[i] - mx, dy = (double)vr[n + i] - my, dz = (double)vr[2 * n + i] - mz;
+            const uint32_t sl = fwd[i];
+            const double dx = (double)V.vx[sl] - mx, dy = (double)V.vy[sl] - my, dz = (double)V.vz[sl] - mz;
             const double d2 = dx * dx + dy * dy + dz * dz;
             sv[0] += dx;
             sv[1] += dy;
@@ -364,6 +363,9 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
         return;
     }
     const Key key{I->seed, I->uid, 0u, I->step};
+    const T* vx = uni(reinterpret_cast<const T*>(I->vx[0]));
+    const T* vy = uni(reinterpret_cast<const T*>(I->vy[0]));
+    const T* vz = uni(reinterpret_cast<const T*>(I->vz[0]));
     CellMem<T> M;
     M.init(I, 0, 0, n);
     Levels L = levels_at(lv, lv_stride);
@@ -376,10 +378,10 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
         const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
         double all[7];
-        attempt_sums<T, G>(M.leaf, I->bsum, n, kept_end, leaf_end, mx, my, mz, tid, gl.red, all);
+        attempt_sums<T, G>(vx, vy, vz, M.fwd, I->bsum, n, kept_end, leaf_end, mx, my, mz, tid, gl.red, all);
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
-        bottom_up<T, G, true>(key, n, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
+        bottom_up<T, G, true>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
         double fs[1] = {sfin};
         gsum<G, 1>(fs, gl.red);
         const uint32_t td = gsum_u32<G>(dummies, gl.redu);
@@ -493,9 +495,10 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
             const uint32_t i = ro[u];
             if (s >= s_end || i < kept_end) continue;
             if (i < leaf_end) {
-                V.vx[s] = M.fin[s];
-                V.vy[s] = M.fin[n + s];
-                V.vz[s] = M.fin[2 * n + s];
+                const uint32_t r = leaf_rank(i, N0, P);  // final r goes to the slot of leaf r
+                V.vx[s] = M.fin[r];
+                V.vy[s] = M.fin[n + r];
+                V.vz[s] = M.fin[2 * n + r];
             } else if (thermalize) {
                 const Vec3<T> z = Draws<T>::normals(key, i - leaf_end);
                 V.vx[s] = (T)(u0 + a * ((double)z.x - z0));
