@@ -125,6 +125,28 @@ def cpu_baseline(N, eps, alpha, init, seed, budget_s=20.0):
                       f"serial FP64 oracle, {t_used:.1f} s"}
 
 
+def serving(T, args):
+    """Serving run: a Poisson stream of homogeneous solves and shock tubes (N
+    log-uniform in [1e3, 1e6], 50-500 steps, eps log-uniform in [1e-4, 1]) served
+    with continuous batching under an HBM budget, arrivals in real time."""
+    import workloads as W
+    from paper_1009_2768_amd.serve import Server, summarize
+    reqs = W.serving_requests(args.serve_rate, args.serve_seconds, seed=args.seed)
+    log(f"serving {len(reqs)} requests over {args.serve_seconds} s ...")
+    srv = Server(hbm_budget=int(args.serve_budget_gib * 2**30), max_instances=4096, max_cells=1 << 21)
+    done = srv.run(reqs, realtime=True)
+    srv.close()
+    out = summarize(done, srv.wall)
+    out.update({"rate_per_s": args.serve_rate, "stream_s": args.serve_seconds,
+                "hbm_budget_gib": args.serve_budget_gib, "peak_hbm_gib": srv.peak_bytes / 2**30,
+                "peak_running": srv.peak_active, "ticks": srv.ticks, "precision": "fp32",
+                "mix": "homogeneous (Maxwell) and Sod tubes (hard spheres) 50/50, N log-uniform [1e3, 1e6], "
+                       "50-500 steps, eps log-uniform [1e-4, 1]"})
+    log(f"serving: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
+        f"{out['particle_steps_per_s']:.3e} particle-steps/s, wall {srv.wall:.2f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +162,10 @@ def main():
     ap.add_argument("--table", default=None,
                     help="fixed schedule instead of tuning, e.g. 8:wave,9:wave,11:group (bucket:path)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one instead of a HIP graph")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of the Poisson request stream of the serving run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="HBM budget of the running requests")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB each (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -237,10 +263,14 @@ def main():
                      "kernel": (kernel + " (+ k_advance, about 4 us)") if not tiled else
                      "tile pipeline + " + kernel + " (several kernels per step)"},
     }
+    ctx.close()
+    del ctx, bufs
+    torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
+        line["serving"] = serving(T, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(N, eps, alpha, init, args.seed, args.cpu_budget)
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

@@ -1,0 +1,186 @@
+"""Serving loop: continuous batching of TRMC-R solves on one GPU.
+
+Requests (homogeneous solves and shock tubes of different sizes, eps and step
+counts) arrive over time.  All running requests share one context and advance
+together, one step per tick (one trmc_step over every active instance).  At each
+tick boundary the loop
+
+  * retires the requests whose last step has run (their moments are read and
+    their device memory is released),
+  * admits waiting requests in arrival order while the HBM budget (particle
+    arrays plus library workspace of the running requests) and the slot and
+    cell capacities allow,
+
+so requests that arrive while others are on the GPU join the running batch as
+soon as memory frees up.  Particle state stays on the device from admission to
+retirement.  A request's result does not depend on what it ran with: the
+library keys every random draw by (seed, uid, cell, step) and every cell's step
+reads only that cell.
+
+Latency is measured from a request's arrival to the moment its results are on
+the host; throughput is particle-steps completed per second of wall time.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _abi
+from . import (ADAPTIVE, FP32_MIXED, FP64, HOMOG, SLAB1D, Context, Instance, check)
+
+
+def instance_of(req, precision=FP32_MIXED, m_cap=64) -> Instance:
+    """Descriptor of a request (see workloads.serving_requests)."""
+    if req["slab"]:
+        nc = int(req["n_cells"])
+        dx = 1.0 / nc
+        return Instance(n_particles=int(req["n"]), geometry=SLAB1D, n_cells=nc, length=1.0,
+                        dt=0.5 * dx / 3.0, particle_weight=dx / int(req["ppc_left"]), eps=float(req["eps"]),
+                        alpha=float(req["alpha"]), trunc=ADAPTIVE, m_cap=m_cap, precision=precision,
+                        seed=int(req["seed"]), uid=int(req["rid"]))
+    n = int(req["n"])
+    return Instance(n_particles=n, eps=float(req["eps"]), alpha=float(req["alpha"]), dt=0.05,
+                    particle_weight=1.0 / n, trunc=ADAPTIVE, m_cap=m_cap, precision=precision,
+                    seed=int(req["seed"]), uid=int(req["rid"]))
+
+
+def workspace_bytes(inst: Instance) -> int:
+    d = inst.to_c()
+    n = ctypes.c_size_t(0)
+    check(_abi.load().trmc_workspace_size(ctypes.byref(d), 1, ctypes.byref(n)), "trmc_workspace_size")
+    return int(n.value)
+
+
+@dataclass
+class Done:
+    rid: int
+    n: int
+    steps: int
+    arrival: float
+    admitted: float
+    finished: float
+    moments: dict = field(repr=False)
+    state: dict | None = field(default=None, repr=False)
+    tick_admitted: int = 0
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+class Server:
+    """One context, a FIFO queue and an HBM budget for the running requests."""
+
+    def __init__(self, hbm_budget: int, max_instances: int = 4096, max_cells: int = 1 << 20,
+                 precision=FP32_MIXED, initial=None, capture=()):
+        import torch
+        self.precision = precision
+        self.dtype = torch.float32 if precision == FP32_MIXED else torch.float64
+        self.budget = int(hbm_budget)
+        self.ctx = Context([], [], max_instances=max_instances, max_cells=max_cells)
+        self.max_instances, self.max_cells = max_instances, max_cells
+        if initial is None:
+            import workloads
+            initial = workloads.serving_initial
+        self.initial = initial
+        self.capture = set(capture)  # rids whose final particles are read back
+        self.used = 0
+        self.cells = 0
+        self.active = {}  # slot -> [req, steps_left, bytes, t_admit, tensors, tick_admit]
+        self.peak_bytes = 0
+        self.peak_active = 0
+        self.ticks = 0
+
+    def cost(self, req):
+        inst = instance_of(req, self.precision)
+        sz = 4 if self.precision == FP32_MIXED else 8
+        arrays = (4 if req["slab"] else 3) * sz * int(req["n"])
+        return inst, arrays + workspace_bytes(inst)
+
+    def fits(self, req, nbytes):
+        cells = int(req["n_cells"]) if req["slab"] else 1
+        return (self.used + nbytes <= self.budget and len(self.active) < self.max_instances
+                and self.cells + cells <= self.max_cells)
+
+    def admit(self, req, inst, nbytes, now):
+        parts = self.initial(req, dtype=self.dtype)
+        slot = self.ctx.admit(inst, parts)
+        self.active[slot] = [req, int(req["steps"]), nbytes, now, parts, self.ticks]
+        self.used += nbytes
+        self.cells += int(req["n_cells"]) if req["slab"] else 1
+        self.peak_bytes = max(self.peak_bytes, self.used)
+        self.peak_active = max(self.peak_active, len(self.active))
+        return slot
+
+    def retire(self, slot, t0):
+        req, _, nbytes, t_adm, _, tick = self.active[slot]
+        mom = self.ctx.moments(slot)  # synchronises: the results are on the host
+        state = self.ctx.read(slot) if req["rid"] in self.capture else None
+        t = time.perf_counter() - t0
+        self.ctx.retire(slot)
+        del self.active[slot]
+        self.used -= nbytes
+        self.cells -= int(req["n_cells"]) if req["slab"] else 1
+        return Done(req["rid"], int(req["n"]), int(req["steps"]), req["arrival"], t_adm, t, mom, state, tick)
+
+    def run(self, requests, realtime: bool = True, log=None):
+        """Serve the requests (sorted by arrival).  realtime: arrivals follow the
+        wall clock (idle gaps are waited out); otherwise every request is queued
+        at time 0.  Returns the list of Done records in completion order."""
+        pending = deque(sorted(requests, key=lambda r: r["arrival"]))
+        waiting = deque()
+        done = []
+        t0 = time.perf_counter()
+        head = None  # (inst, bytes) of waiting[0]
+        while pending or waiting or self.active:
+            now = time.perf_counter() - t0
+            while pending and (not realtime or pending[0]["arrival"] <= now):
+                r = pending.popleft()
+                if not realtime:
+                    r = dict(r, arrival=0.0)
+                waiting.append(r)
+            # admission at the tick boundary, in arrival order
+            while waiting:
+                if head is None:
+                    head = self.cost(waiting[0])
+                inst, nbytes = head
+                if not self.fits(waiting[0], nbytes):
+                    if not self.active:
+                        raise RuntimeError(f"request {waiting[0]['rid']} does not fit in an empty server")
+                    break
+                self.admit(waiting.popleft(), inst, nbytes, now)
+                head = None
+            if not self.active:
+                if pending:
+                    time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
+                continue
+            self.ctx.step(1)
+            self.ticks += 1
+            finished = []
+            for slot, st in self.active.items():
+                st[1] -= 1
+                if st[1] == 0:
+                    finished.append(slot)
+            for slot in finished:
+                done.append(self.retire(slot, t0))
+            if log and finished:
+                log(f"t={time.perf_counter() - t0:.3f}s tick {self.ticks}: {len(finished)} done, "
+                    f"{len(self.active)} running, {len(waiting)} waiting, {self.used / 2**30:.2f} GiB")
+        self.wall = time.perf_counter() - t0
+        return done
+
+    def close(self):
+        self.ctx.close()
+
+
+def summarize(done, wall):
+    lat = np.array([d.latency for d in done]) * 1e3
+    ps = sum(d.n * d.steps for d in done)
+    return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_ms": float(lat.mean()) if len(lat) else None,
+            "particle_steps_per_s": ps / wall if wall > 0 else None, "particle_steps": ps, "wall_s": wall}

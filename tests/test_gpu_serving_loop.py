@@ -1,0 +1,87 @@
+"""GPU: the serving loop (continuous batching under an HBM budget).
+
+A Poisson stream of homogeneous solves and shock tubes is served with a budget
+that holds only a few requests at once, so requests wait, are admitted while
+others run and retire at different ticks.  Every request completes, the budget
+is never exceeded, and each captured result is bitwise the same as the same
+request run alone in a fresh context (FP32-mixed and FP64).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm GPU"
+    import paper_1009_2768_amd as T
+    T.load()
+    return T
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def alone(T, req, precision):
+    import torch
+    from paper_1009_2768_amd.serve import instance_of
+    inst = instance_of(req, precision)
+    dt = torch.float32 if precision == T.FP32_MIXED else torch.float64
+    parts = W.serving_initial(req, dtype=dt)
+    ctx = T.Context([inst], [parts])
+    ctx.step(int(req["steps"]))
+    out = ctx.read(0)
+    mom = ctx.moments(0)
+    ctx.close()
+    return out, mom
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_served_results_equal_alone(T, prec):
+    from paper_1009_2768_amd.serve import Server, summarize
+    precision = T.FP32_MIXED if prec == "fp32" else T.FP64
+    reqs = W.serving_requests(rate=60.0, duration=0.25, seed=3, n_min=500, n_max=20000, steps_min=3,
+                              steps_max=12, ppc_left=64)
+    say(f"serving {len(reqs)} requests ({prec}), slabs {sum(r['slab'] for r in reqs)}")
+    assert len(reqs) >= 8
+    probe = [r["rid"] for r in reqs[:: max(1, len(reqs) // 5)]]
+    srv = Server(hbm_budget=0, precision=precision, max_instances=64, max_cells=1 << 16, capture=probe)
+    # a budget of about three average requests: requests must queue and join later
+    costs = [srv.cost(r)[1] for r in reqs]
+    srv.budget = int(max(max(costs), 3 * np.mean(costs)))
+    done = srv.run(reqs, realtime=False)
+    srv.close()
+    assert sorted(d.rid for d in done) == [r["rid"] for r in reqs]
+    assert srv.peak_bytes <= srv.budget
+    assert srv.peak_active >= 2
+    late = [d for d in done if d.tick_admitted > 0]
+    assert late, "no request was admitted while others ran"
+    st = summarize(done, srv.wall)
+    say(f"p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, {st['particle_steps_per_s']:.3e} ps/s")
+    by = {d.rid: d for d in done}
+    for rid in probe:
+        req = next(r for r in reqs if r["rid"] == rid)
+        ref, mom = alone(T, req, precision)
+        got = by[rid].state
+        for c in ("x", "vx", "vy", "vz"):
+            if ref[c] is not None:
+                assert np.array_equal(ref[c], got[c]), (rid, c)
+        assert np.array_equal(np.asarray(mom["m_state"]), np.asarray(by[rid].moments["m_state"]))
+        assert np.array_equal(np.asarray(mom["collisions"]), np.asarray(by[rid].moments["collisions"]))
+
+
+def test_request_larger_than_budget_is_rejected(T):
+    from paper_1009_2768_amd.serve import Server
+    reqs = W.serving_requests(rate=50.0, duration=0.1, seed=5, n_min=5000, n_max=6000, steps_min=2, steps_max=3)
+    srv = Server(hbm_budget=1024, max_instances=8, max_cells=1 << 12)
+    with pytest.raises(RuntimeError):
+        srv.run(reqs, realtime=False)
+    srv.close()

@@ -124,3 +124,69 @@ def batched_velocities(N, init, seed: int = 0, K0: float = 0.6):
         a = bkw(int(n), K0, seed, 1000 + i) if kind == 0 else bimaxwellian(int(n), seed, 1000 + i)
         vx.append(a[0]); vy.append(a[1]); vz.append(a[2])
     return np.concatenate(vx), np.concatenate(vy), np.concatenate(vz)
+
+
+def serving_requests(rate: float, duration: float, seed: int = 0, n_min: int = 1000, n_max: int = 1_000_000,
+                     steps_min: int = 50, steps_max: int = 500, eps_min: float = 1e-4, eps_max: float = 1.0,
+                     slab_fraction: float = 0.5, ppc_left: int = 512):
+    """A Poisson request stream for the serving loop.
+
+    Arrivals with exponential gaps of mean 1/rate over [0, duration); each request
+    is a homogeneous solve (Maxwell molecules, bi-Maxwellian or BKW-like initial
+    data) or a Sod-type shock tube (hard spheres), with N log-uniform in [n_min,
+    n_max], a step count uniform in [steps_min, steps_max] and eps log-uniform in
+    [eps_min, eps_max].  A tube has ppc_left particles per cell on its left half
+    and ppc_left / 8 on its right half (density ratio 0.125), so n_cells is about
+    N / (9 ppc_left / 16), kept within [2, 12288].
+    """
+    g = rng(seed, 11)
+    out, t, rid = [], 0.0, 0
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        n = int(round(n_min * (n_max / n_min) ** g.random()))
+        steps = int(g.integers(steps_min, steps_max + 1))
+        eps = float(eps_min * (eps_max / eps_min) ** g.random())
+        slab = bool(g.random() < slab_fraction)
+        req = {"rid": rid, "arrival": t, "slab": slab, "steps": steps, "eps": eps, "seed": seed,
+               "alpha": 1.0 if slab else 0.0, "init": int(g.integers(0, 2))}
+        if slab:
+            nc = int(min(12288, max(2, round(n / (9 * ppc_left / 16)))))
+            left = nc // 2
+            ppc_r = max(1, ppc_left // 8)
+            req.update(n_cells=nc, ppc_left=ppc_left, ppc_right=ppc_r,
+                       n=left * ppc_left + (nc - left) * ppc_r)
+        else:
+            req.update(n_cells=1, n=n)
+        out.append(req)
+        rid += 1
+    return out
+
+
+def serving_initial(req, device="cuda", dtype=None):
+    """Initial particles of a serving request, drawn on the device with a torch
+    generator seeded by (seed, rid): deterministic for a given device, whether the
+    request runs alone or in a mix.  Returns dict(x, vx, vy, vz) of tensors."""
+    import torch
+    dtype = dtype or torch.float32
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(req["seed"]) * 1_000_003 + int(req["rid"]) + 1)
+    n = int(req["n"])
+    if req["slab"]:
+        nc, left = int(req["n_cells"]), int(req["n_cells"]) // 2
+        pl, pr = int(req["ppc_left"]), int(req["ppc_right"])
+        counts = torch.tensor([pl] * left + [pr] * (nc - left), device=device)
+        cell = torch.repeat_interleave(torch.arange(nc, device=device), counts)
+        dx = 1.0 / nc
+        x = (cell.to(torch.float64) + torch.rand(n, generator=gen, device=device, dtype=torch.float64)) * dx
+        sd = torch.where(cell < left, torch.tensor(1.0, device=device), torch.tensor(math.sqrt(0.8), device=device))
+        v = torch.randn(3, n, generator=gen, device=device, dtype=torch.float64) * sd.to(torch.float64)
+        return {"x": x.to(dtype), "vx": v[0].to(dtype).contiguous(), "vy": v[1].to(dtype).contiguous(),
+                "vz": v[2].to(dtype).contiguous()}
+    v = torch.randn(3, n, generator=gen, device=device, dtype=torch.float64)
+    if req["init"] == 1:  # bi-Maxwellian: means +-1 along x
+        sign = torch.where(torch.arange(n, device=device) % 2 == 0, 1.0, -1.0).to(torch.float64)
+        v[0] += sign
+    return {"x": None, "vx": v[0].to(dtype).contiguous(), "vy": v[1].to(dtype).contiguous(),
+            "vz": v[2].to(dtype).contiguous()}
