@@ -93,6 +93,12 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     CellStats* st = I->stats + cell;
     const Key key = uni(Key{I->seed, I->uid, cell, I->step});
 
+#ifndef TRMC_PRIO_CELL
+#define TRMC_PRIO_CELL 16384u
+#endif
+    // the largest cells carry the longest dependent chains of the launch: their
+    // waves take issue priority over the small cells sharing their compute unit
+    if (n >= TRMC_PRIO_CELL) __builtin_amdgcn_s_setprio(2);
     if (n < 2) {
         if (tid == 0) {
             CellStats s{};
