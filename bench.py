@@ -134,12 +134,17 @@ def serving(T, args):
     reqs = W.serving_requests(args.serve_rate, args.serve_seconds, seed=args.seed)
     log(f"serving {len(reqs)} requests over {args.serve_seconds} s ...")
     srv = Server(hbm_budget=int(args.serve_budget_gib * 2**30), max_instances=4096, max_cells=1 << 21)
+    t0 = time.time()
+    table, _ = srv.tune(reqs, log=log)  # outside the served stream
+    names = ["default", "group", "wave", "tiled"]
+    log(f"serving schedule tuned in {time.time() - t0:.1f} s")
     done = srv.run(reqs, realtime=True)
     srv.close()
     out = summarize(done, srv.wall)
     out.update({"rate_per_s": args.serve_rate, "stream_s": args.serve_seconds,
                 "hbm_budget_gib": args.serve_budget_gib, "peak_hbm_gib": srv.peak_bytes / 2**30,
                 "peak_running": srv.peak_active, "ticks": srv.ticks, "precision": "fp32",
+                "schedule": {f"2^{b}": names[p] for b, p in enumerate(table) if p},
                 "mix": "homogeneous (Maxwell) and Sod tubes (hard spheres) 50/50, N log-uniform [1e3, 1e6], "
                        "50-500 steps, eps log-uniform [1e-4, 1]"})
     log(f"serving: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "

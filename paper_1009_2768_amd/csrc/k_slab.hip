@@ -67,14 +67,20 @@ __host__ __device__ inline uint32_t sort_tile(uint32_t n_cells)
     return t < kSortTile ? kSortTile : t;
 }
 
+// The sort kernels run every slab of a precision in one launch: flat block t is
+// tile k of slab b (tile_of over the prefix of the slabs' tile counts).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_hist(InstDev* __restrict__ I)
+__global__ __launch_bounds__(1024) void k_hist(const CellRef* __restrict__ slabs, const uint32_t* __restrict__ prefix,
+                                               uint32_t ns)
 {
     extern __shared__ uint32_t hist[];
+    uint32_t b, kt;
+    tile_of(prefix, ns, blockIdx.x, b, kt);
+    InstDev* __restrict__ I = slabs[b].inst;
     const uint32_t nc = I->n_cells;
     const uint32_t tile = sort_tile(nc);
     const uint64_t n = I->n;
-    const uint64_t t0 = (uint64_t)blockIdx.x * tile;
+    const uint64_t t0 = (uint64_t)kt * tile;
     const uint64_t t1 = (t0 + tile < n) ? t0 + tile : n;
     for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) hist[c] = 0;
     __syncthreads();
@@ -89,15 +95,20 @@ __global__ __launch_bounds__(1024) void k_hist(InstDev* __restrict__ I)
         atomicAdd(&hist[c], 1u);
     }
     __syncthreads();
-    uint32_t* out = I->hist + (uint64_t)blockIdx.x * nc;
+    uint32_t* out = I->hist + (uint64_t)kt * nc;
     for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) out[c] = hist[c];
 }
 
-// Column scan over tiles: hist[t][c] <- sum_{t' < t} hist[t'][c]; totals to cell_off.
-__global__ __launch_bounds__(256) void k_scan_tiles(InstDev* __restrict__ I)
+// Column scan over tiles: hist[t][c] <- sum_{t' < t} hist[t'][c]; totals to
+// cell_off.  Flat block t is block k (256 cells) of slab b.
+__global__ __launch_bounds__(256) void k_scan_tiles(const CellRef* __restrict__ slabs,
+                                                    const uint32_t* __restrict__ prefix, uint32_t ns)
 {
+    uint32_t b, kb;
+    tile_of(prefix, ns, blockIdx.x, b, kb);
+    InstDev* __restrict__ I = slabs[b].inst;
     const uint32_t nc = I->n_cells;
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t c = kb * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     const uint32_t nt = I->n_tiles;
     uint32_t acc = 0;
@@ -110,10 +121,11 @@ __global__ __launch_bounds__(256) void k_scan_tiles(InstDev* __restrict__ I)
     I->cell_off[c + 1] = acc;  // counts, scanned by k_scan_cells
 }
 
-// Exclusive scan of the cell counts (one workgroup of 1024 threads).
-__global__ __launch_bounds__(1024) void k_scan_cells(InstDev* __restrict__ I)
+// Exclusive scan of the cell counts (one workgroup of 1024 threads per slab).
+__global__ __launch_bounds__(1024) void k_scan_cells(const CellRef* __restrict__ slabs)
 {
     __shared__ uint32_t part[1024];
+    InstDev* __restrict__ I = slabs[blockIdx.x].inst;
     const uint32_t nc = I->n_cells;
     const uint32_t per = (nc + 1023u) / 1024u;
     const uint32_t b = threadIdx.x * per;
@@ -139,19 +151,23 @@ __global__ __launch_bounds__(1024) void k_scan_cells(InstDev* __restrict__ I)
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_scatter(InstDev* __restrict__ I)
+__global__ __launch_bounds__(1024) void k_scatter(const CellRef* __restrict__ slabs,
+                                                  const uint32_t* __restrict__ prefix, uint32_t ns)
 {
     extern __shared__ uint32_t run[];              // [nc] next destination of each cell in this tile
     __shared__ uint32_t wl_cell[16][64];           // per-wave distinct cells of the chunk
     __shared__ uint32_t wl_cnt[16][64];
     __shared__ uint32_t wl_pre[16][64];
     __shared__ uint32_t wl_n[16];
+    uint32_t b, kt;
+    tile_of(prefix, ns, blockIdx.x, b, kt);
+    InstDev* __restrict__ I = slabs[b].inst;
     const uint32_t nc = I->n_cells;
     const uint32_t tile = sort_tile(nc);
     const uint64_t n = I->n;
-    const uint64_t t0 = (uint64_t)blockIdx.x * tile;
+    const uint64_t t0 = (uint64_t)kt * tile;
     const uint64_t t1 = (t0 + tile < n) ? t0 + tile : n;
-    const uint32_t* base = I->hist + (uint64_t)blockIdx.x * nc;
+    const uint32_t* base = I->hist + (uint64_t)kt * nc;
     for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) run[c] = I->cell_off[c] + base[c];
     __syncthreads();
     const uint32_t cur = I->cur, nxt = cur ^ 1u;
@@ -284,10 +300,10 @@ __global__ void k_advance(InstDev* const* __restrict__ insts, uint32_t n_inst)
     if (I->geometry == GEOM_SLAB) I->cur ^= 1u;
 }
 
-template __global__ void k_hist<float>(InstDev*);
-template __global__ void k_hist<double>(InstDev*);
-template __global__ void k_scatter<float>(InstDev*);
-template __global__ void k_scatter<double>(InstDev*);
+template __global__ void k_hist<float>(const CellRef*, const uint32_t*, uint32_t);
+template __global__ void k_hist<double>(const CellRef*, const uint32_t*, uint32_t);
+template __global__ void k_scatter<float>(const CellRef*, const uint32_t*, uint32_t);
+template __global__ void k_scatter<double>(const CellRef*, const uint32_t*, uint32_t);
 template __global__ void k_moments<float>(const CellRef*, uint32_t);
 template __global__ void k_moments<double>(const CellRef*, uint32_t);
 

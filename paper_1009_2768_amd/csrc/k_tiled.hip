@@ -42,19 +42,6 @@ __device__ __forceinline__ uint32_t* big_levels(const InstDev* I)
     return reinterpret_cast<uint32_t*>(I->bigstate + kBigStateBytes);
 }
 
-// Tile -> (large cell, tile index within the cell) by binary search of the prefix.
-__device__ __forceinline__ void tile_of(const uint32_t* prefix, uint32_t nb, uint32_t t, uint32_t& b, uint32_t& k)
-{
-    uint32_t lo = 0, hi = nb;  // prefix[lo] <= t < prefix[hi]
-    while (hi - lo > 1u) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (prefix[mid] <= t) lo = mid;
-        else hi = mid;
-    }
-    b = lo;
-    k = t - prefix[lo];
-}
-
 template <typename T>
 struct CellView {
     InstDev* I;

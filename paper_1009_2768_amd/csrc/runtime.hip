@@ -17,11 +17,11 @@ namespace trmc {
 template <typename T>
 __global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
 template <typename T>
-__global__ void k_hist(InstDev*);
-__global__ void k_scan_tiles(InstDev*);
-__global__ void k_scan_cells(InstDev*);
+__global__ void k_hist(const CellRef*, const uint32_t*, uint32_t);
+__global__ void k_scan_tiles(const CellRef*, const uint32_t*, uint32_t);
+__global__ void k_scan_cells(const CellRef*);
 template <typename T>
-__global__ void k_scatter(InstDev*);
+__global__ void k_scatter(const CellRef*, const uint32_t*, uint32_t);
 template <typename T>
 __global__ void k_moments(const CellRef*, uint32_t);
 struct CellLists {
@@ -158,6 +158,11 @@ struct trmc_ctx {
     uint32_t n_tiles[2] = {0, 0};
     uint32_t* cls_list[2] = {nullptr, nullptr};   // [2 * max_cells] light / heavy cells of the step
     uint32_t* cls_count[2] = {nullptr, nullptr};  // [2]
+    // slabs of each precision, sorted together: tile and 256-cell block prefixes
+    CellRef* slab_refs[2] = {nullptr, nullptr};
+    uint32_t* slab_tpre[2] = {nullptr, nullptr};
+    uint32_t* slab_cpre[2] = {nullptr, nullptr};
+    uint32_t n_slab[2] = {0, 0}, slab_tiles[2] = {0, 0}, slab_cblk[2] = {0, 0}, slab_maxnc[2] = {0, 0};
     InstDev** inst_ptrs = nullptr;
     uint32_t n_active = 0;
     uint32_t cells_used = 0;
@@ -179,6 +184,7 @@ size_t ctx_bytes(uint32_t max_inst, uint32_t max_cells)
     return al(sizeof(uint32_t)) + 6 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
            2 * al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1)) +
            2 * (al(sizeof(uint32_t) * 2 * std::max(1u, max_cells)) + al(2 * sizeof(uint32_t))) +
+           2 * (al(sizeof(CellRef) * max_inst) + 2 * al(sizeof(uint32_t) * (max_inst + 1))) +
            al(sizeof(InstDev*) * std::max(1u, max_inst));
 }
 
@@ -239,6 +245,37 @@ int rebuild_tables(trmc_ctx* c)
                 if (e != hipSuccess) return TRMC_EIO;
             }
         }
+    }
+    // slab sort tables, per precision
+    std::vector<CellRef> sref[2];
+    std::vector<uint32_t> tpre[2], cpre[2];
+    for (int k = 0; k < 2; ++k) {
+        tpre[k].assign(1, 0u);
+        cpre[k].assign(1, 0u);
+        c->slab_maxnc[k] = 0;
+    }
+    for (auto& s : c->slots) {
+        if (!s.active || s.host.geometry != GEOM_SLAB) continue;
+        const int k = s.host.precision == PREC_FP64 ? 1 : 0;
+        sref[k].push_back(CellRef{s.dev, 0, 0});
+        tpre[k].push_back(tpre[k].back() + s.lay.n_tiles);
+        cpre[k].push_back(cpre[k].back() + (s.host.n_cells + 255u) / 256u);
+        c->slab_maxnc[k] = std::max(c->slab_maxnc[k], s.host.n_cells);
+    }
+    for (int k = 0; k < 2; ++k) {
+        c->n_slab[k] = (uint32_t)sref[k].size();
+        c->slab_tiles[k] = tpre[k].back();
+        c->slab_cblk[k] = cpre[k].back();
+        if (sref[k].empty()) continue;
+        hipError_t e = hipMemcpyAsync(c->slab_refs[k], sref[k].data(), sizeof(CellRef) * sref[k].size(),
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->slab_tpre[k], tpre[k].data(), sizeof(uint32_t) * tpre[k].size(),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->slab_cpre[k], cpre[k].data(), sizeof(uint32_t) * cpre[k].size(),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return TRMC_EIO;
     }
     if (!ptrs.empty()) {
         hipError_t e = hipMemcpyAsync(c->inst_ptrs, ptrs.data(), sizeof(InstDev*) * ptrs.size(),
@@ -368,16 +405,21 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     return 0;
 }
 
+// Transport and counting sort of every slab of precision k (T), four launches
+// whatever the number of slabs.
 template <typename T>
-int launch_slab(trmc_ctx* c, Slot& s)
+int launch_slabs(trmc_ctx* c, int k)
 {
-    const uint32_t nc = s.host.n_cells;
-    const uint32_t nt = s.lay.n_tiles;
-    if (nt == 0) return 0;
-    hipLaunchKernelGGL(k_hist<T>, dim3(nt), dim3(1024), sizeof(uint32_t) * nc, c->stream, s.dev);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((nc + 255) / 256), dim3(256), 0, c->stream, s.dev);
-    hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, c->stream, s.dev);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(nt), dim3(1024), sizeof(uint32_t) * nc, c->stream, s.dev);
+    const uint32_t ns = c->n_slab[k];
+    if (ns == 0 || c->slab_tiles[k] == 0) return 0;
+    const size_t lds = sizeof(uint32_t) * c->slab_maxnc[k];
+    hipLaunchKernelGGL(k_hist<T>, dim3(c->slab_tiles[k]), dim3(1024), lds, c->stream, c->slab_refs[k],
+                       c->slab_tpre[k], ns);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(c->slab_cblk[k]), dim3(256), 0, c->stream, c->slab_refs[k],
+                       c->slab_cpre[k], ns);
+    hipLaunchKernelGGL(k_scan_cells, dim3(ns), dim3(1024), 0, c->stream, c->slab_refs[k]);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(c->slab_tiles[k]), dim3(1024), lds, c->stream, c->slab_refs[k],
+                       c->slab_tpre[k], ns);
     return hip_status(hipGetLastError());
 }
 
@@ -495,6 +537,14 @@ int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trm
         c->cls_count[k] = reinterpret_cast<uint32_t*>(c->ws + p);
         p += al(2 * sizeof(uint32_t));
     }
+    for (int k = 0; k < 2; ++k) {
+        c->slab_refs[k] = reinterpret_cast<CellRef*>(c->ws + p);
+        p += al(sizeof(CellRef) * max_instances);
+        c->slab_tpre[k] = reinterpret_cast<uint32_t*>(c->ws + p);
+        p += al(sizeof(uint32_t) * (max_instances + 1));
+        c->slab_cpre[k] = reinterpret_cast<uint32_t*>(c->ws + p);
+        p += al(sizeof(uint32_t) * (max_instances + 1));
+    }
     c->inst_ptrs = reinterpret_cast<InstDev**>(c->ws + p);
     p += al(sizeof(InstDev*) * std::max(1u, max_instances));
     if (hipMemsetAsync(c->error, 0, sizeof(uint32_t), c->stream) != hipSuccess) {
@@ -545,11 +595,7 @@ int enqueue_step(trmc_ctx* c, hipStream_t st)
     const hipStream_t keep = c->stream;
     c->stream = st;
     int rc = 0;
-    for (auto& s : c->slots) {
-        if (!s.active || s.host.geometry != GEOM_SLAB) continue;
-        rc = s.host.precision == PREC_FP64 ? launch_slab<double>(c, s) : launch_slab<float>(c, s);
-        if (rc) break;
-    }
+    for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_slabs<float>(c, 0) : launch_slabs<double>(c, 1);
     for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_collide<float>(c, 0) : launch_collide<double>(c, 1);
     if (!rc && c->n_active)
         hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, st, c->inst_ptrs,

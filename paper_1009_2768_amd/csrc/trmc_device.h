@@ -112,6 +112,20 @@ __device__ __forceinline__ double exp_neg(double x)
     return ldexp(p, (int)k);
 }
 
+// Item b and local index k of flat block t, given the exclusive prefix of the
+// items' block counts (prefix[b] <= t < prefix[b + 1]; nb items).
+__device__ __forceinline__ void tile_of(const uint32_t* prefix, uint32_t nb, uint32_t t, uint32_t& b, uint32_t& k)
+{
+    uint32_t lo = 0, hi = nb;  // prefix[lo] <= t < prefix[hi]
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    b = lo;
+    k = t - prefix[lo];
+}
+
 // Round a positive double up to 20 significant bits (grid of the VHS majorant).
 __device__ __forceinline__ double grid_up20(double g)
 {

@@ -95,6 +95,25 @@ class Server:
         self.peak_active = 0
         self.ticks = 0
 
+    def tune(self, requests, per_bucket: int = 2, log=None):
+        """Choose the kernel path per cell-size bucket with the autotuner, timed on
+        copies of up to per_bucket requests of each bucket (before serving)."""
+        from . import size_bucket
+        from .autotune import autotune
+        picked, count = [], {}
+        for r in requests:
+            inst = instance_of(r, self.precision)
+            b = size_bucket(inst)
+            if count.get(b, 0) < per_bucket:
+                count[b] = count.get(b, 0) + 1
+                picked.append((inst, r))
+        insts = [i for i, _ in picked]
+        parts = [self.initial(r, dtype=self.dtype) for _, r in picked]
+        table, timings = autotune(insts, parts, warmup=1, steps=2, log=log)
+        self.ctx.set_schedule(table)
+        self.schedule = table
+        return table, timings
+
     def cost(self, req):
         inst = instance_of(req, self.precision)
         sz = 4 if self.precision == FP32_MIXED else 8
