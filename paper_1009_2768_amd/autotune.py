@@ -48,11 +48,13 @@ def _time_path(insts, parts, path, warmup, steps):
         ctx.close()
 
 
-def autotune(instances, particles, warmup=1, steps=2, max_particles=8_000_000, log=None):
+def autotune(instances, particles, warmup=1, steps=2, max_particles=8_000_000, margin=0.05, log=None):
     """Return (schedule table, per-bucket timings in ms) for these instances.
 
     particles[i] holds the device tensors of instances[i]; they are copied, never
-    stepped.  At most max_particles particles of a bucket are used to time it.
+    stepped.  At most max_particles particles of a bucket are used to time it.  A
+    path other than the workgroup path is chosen only when it is faster by more
+    than `margin` (relative).
     """
     buckets: dict[int, list[int]] = {}
     for k, inst in enumerate(instances):
@@ -72,7 +74,11 @@ def autotune(instances, particles, warmup=1, steps=2, max_particles=8_000_000, l
         t0 = time.perf_counter()
         for path in candidates(insts):
             res[path] = _time_path(insts, parts, path, warmup, steps)
+        # the first candidate (workgroup per cell) stays unless another is clearly
+        # faster, so that near-ties do not flip the table from run to run
         best = min(res, key=res.get)
+        if res[best] > (1.0 - margin) * res[PATH_GROUP]:
+            best = PATH_GROUP
         table[b] = best
         timings[b] = res
         if log:

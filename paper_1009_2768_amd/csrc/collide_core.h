@@ -261,16 +261,34 @@ struct GroupLds {
 
 
 // Pointers into one cell's scratch region (layout in trmc_internal.h).
+// A velocity in scratch memory: one aligned 4-component record.
+template <typename T>
+struct alignas(16) Pack4 {
+    T x, y, z, w;
+};
+
+template <typename T>
+__device__ __forceinline__ Vec3<T> unpack(const Pack4<T>& p)
+{
+    return Vec3<T>{p.x, p.y, p.z};
+}
+
+template <typename T>
+__device__ __forceinline__ Pack4<T> pack(T x, T y, T z)
+{
+    return Pack4<T>{x, y, z, T(0)};
+}
+
 template <typename T>
 struct CellMem {
     uint32_t* role;  // [n] role index of each slot (inverse of the keyed permutation)
     uint32_t* fwd;   // [n] slot of each role index (the permutation itself; tile path)
-    T* leaf;         // [3][n] leaves by leaf rank (whole-cell path)
-    T* fin;          // [3][n] finals by leaf rank (final r goes to the slot of leaf r)
+    Pack4<T>* leaf;  // [n] leaves by leaf rank (whole-cell path)
+    Pack4<T>* fin;   // [n] finals by leaf rank (final r goes to the slot of leaf r)
     uint32_t* jarr;  // [cap] sub-level choice of each collision
     uint32_t* rA;    // [cap] rank of request A at level j
     uint32_t* rB;    // [cap] rank of request B at level l-1-j
-    T* outv;         // [3][2 cap] outputs taken by requests
+    Pack4<T>* outv;  // [2 cap] outputs taken by requests
     uint64_t cap, ocap;
     __device__ __forceinline__ void init(const InstDev* I, uint32_t off, uint32_t cell, uint32_t n)
     {
@@ -282,17 +300,17 @@ struct CellMem {
         base += align16(4ull * n);
         fwd = reinterpret_cast<uint32_t*>(base);
         base += align16(4ull * n);
-        leaf = reinterpret_cast<T*>(base);
-        base += 3 * align16(sizeof(T) * (uint64_t)n);
-        fin = reinterpret_cast<T*>(base);
-        base += 3 * align16(sizeof(T) * (uint64_t)n);
+        leaf = reinterpret_cast<Pack4<T>*>(base);
+        base += sizeof(Pack4<T>) * (uint64_t)n;
+        fin = reinterpret_cast<Pack4<T>*>(base);
+        base += sizeof(Pack4<T>) * (uint64_t)n;
         jarr = reinterpret_cast<uint32_t*>(base);
         base += align16(4ull * cap);
         rA = reinterpret_cast<uint32_t*>(base);
         base += align16(4ull * cap);
         rB = reinterpret_cast<uint32_t*>(base);
         base += align16(4ull * cap);
-        outv = reinterpret_cast<T*>(base);
+        outv = reinterpret_cast<Pack4<T>*>(base);
     }
 };
 
@@ -577,14 +595,15 @@ __device__ __forceinline__ uint32_t leaf_role(uint32_t r, uint32_t N0, uint32_t 
 
 // Leaves and sums of the unchanged and thermalized sets over slots [s_begin,
 // s_end) of a cell with NT threads (this thread's share): leaf r is copied to
-// leaf[r]; sums = {kept (vx-m)^2, thermalized (vx-m)^2, thermalized v-m (3),
-// thermalized |v-m|^2}.  Roles below kept_end are unchanged, roles from
-// leaf_end on are thermalized, the others are leaves.
+// leaf[r] unless r < r_done (already there from an earlier attempt: the leaf of
+// a rank does not depend on the depth); sums = {kept (vx-m)^2, thermalized
+// (vx-m)^2, thermalized v-m (3), thermalized |v-m|^2}.  Roles below kept_end
+// are unchanged, roles from leaf_end on are thermalized, the others are leaves.
 template <typename T, int NT>
-__device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* vz, const uint32_t* role, T* leaf,
+__device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* vz, const uint32_t* role, Pack4<T>* leaf,
                                             uint32_t n, uint32_t N0, uint32_t s_begin, uint32_t s_end,
-                                            uint32_t kept_end, uint32_t leaf_end, double mx, double my, double mz,
-                                            uint32_t tid, double (&sums)[6])
+                                            uint32_t kept_end, uint32_t leaf_end, uint32_t r_done, double mx,
+                                            double my, double mz, uint32_t tid, double (&sums)[6])
 {
     constexpr int U = 4;
     const uint32_t P = n - N0;
@@ -609,9 +628,7 @@ __device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* v
                 sums[0] += d * d;
             } else if (i < leaf_end) {
                 const uint32_t r = leaf_rank(i, N0, P);
-                leaf[r] = ax[u];
-                leaf[n + r] = ay[u];
-                leaf[2 * n + r] = az[u];
+                if (r >= r_done) leaf[r] = pack(ax[u], ay[u], az[u]);
             } else {
                 const double dx = (double)ax[u] - mx, dy = (double)ay[u] - my, dz = (double)az[u] - mz;
                 sums[1] += dx * dx;
@@ -642,7 +659,6 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const T* v
                                           uint32_t& dummies, uint32_t& viol, double& sfin)
 {
     const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
-    const uint64_t ocap = M.ocap;
     unsigned long long above = ncoll;  // collisions of deeper levels precede level l's
     uint32_t fp = 0;                   // finals of shallower levels
     for (uint32_t l = 1; l <= me; ++l) {
@@ -666,22 +682,20 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const T* v
                         const uint32_t sl = M.fwd[leaf_role(ra, N0, P)];
                         a[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
                     } else {
-                        a[k] = Vec3<T>{M.leaf[ra], M.leaf[n + ra], M.leaf[2 * n + ra]};
+                        a[k] = unpack(M.leaf[ra]);
                     }
                 } else {
-                    const uint64_t p = (uint64_t)L.outoff[j] + ra;
-                    a[k] = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
+                    a[k] = unpack(M.outv[(uint64_t)L.outoff[j] + ra]);
                 }
                 if (h == 0) {
                     if constexpr (FromSlots) {
                         const uint32_t sl = M.fwd[leaf_role(rb, N0, P)];
                         b[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
                     } else {
-                        b[k] = Vec3<T>{M.leaf[rb], M.leaf[n + rb], M.leaf[2 * n + rb]};
+                        b[k] = unpack(M.leaf[rb]);
                     }
                 } else {
-                    const uint64_t p = (uint64_t)L.outoff[h] + rb;
-                    b[k] = Vec3<T>{M.outv[p], M.outv[ocap + p], M.outv[2 * ocap + p]};
+                    b[k] = unpack(M.outv[(uint64_t)L.outoff[h] + rb]);
                 }
             }
 #pragma unroll
@@ -696,15 +710,10 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const T* v
                 for (int e = 0; e < 2; ++e) {
                     const uint32_t o = 2u * c + (uint32_t)e;
                     if (o < Rl) {
-                        const uint64_t p = (uint64_t)oo + o;
-                        M.outv[p] = out[e].x;
-                        M.outv[ocap + p] = out[e].y;
-                        M.outv[2 * ocap + p] = out[e].z;
+                        M.outv[(uint64_t)oo + o] = pack(out[e].x, out[e].y, out[e].z);
                     } else {
                         const uint32_t r = fp + (o - Rl);
-                        M.fin[r] = out[e].x;
-                        M.fin[n + r] = out[e].y;
-                        M.fin[2 * n + r] = out[e].z;
+                        M.fin[r] = pack(out[e].x, out[e].y, out[e].z);
                         const double d = (double)out[e].x - mx;
                         sfin += d * d;
                     }

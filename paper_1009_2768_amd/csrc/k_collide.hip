@@ -222,6 +222,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     const T gT = (T)sh.g;
 
     // ---- 3. attempts ------------------------------------------------------------
+    uint32_t leaves_done = 0;  // leaf ranks [0, leaves_done) are gathered
     for (;;) {
         split_levels<G>(key, n, sh.q, L, sh, tid);
         TRMC_PHASE(1);
@@ -233,7 +234,9 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
         const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
         double sums[6] = {0, 0, 0, 0, 0, 0};
-        gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, mx, my, mz, tid, sums);
+        gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done, mx, my, mz,
+                          tid, sums);
+        leaves_done = R0 > leaves_done ? R0 : leaves_done;
         gsync<G>();  // leaves visible
         TRMC_PHASE(3);
 
@@ -337,9 +340,10 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
                 const uint32_t i = ro[u];
                 const bool lf = s0 + u * G < n && i >= kept_end && i < leaf_end;
                 const uint32_t r = lf ? leaf_rank(i, N0, P) : 0u;
-                fx[u] = lf ? M.fin[r] : T(0);
-                fy[u] = lf ? M.fin[n + r] : T(0);
-                fz[u] = lf ? M.fin[2 * n + r] : T(0);
+                const Pack4<T> f = M.fin[lf ? r : 0u];
+                fx[u] = f.x;
+                fy[u] = f.y;
+                fz[u] = f.z;
             }
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {

@@ -483,9 +483,10 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
             if (s >= s_end || i < kept_end) continue;
             if (i < leaf_end) {
                 const uint32_t r = leaf_rank(i, N0, P);  // final r goes to the slot of leaf r
-                V.vx[s] = M.fin[r];
-                V.vy[s] = M.fin[n + r];
-                V.vz[s] = M.fin[2 * n + r];
+                const Pack4<T> f = M.fin[r];
+                V.vx[s] = f.x;
+                V.vy[s] = f.y;
+                V.vz[s] = f.z;
             } else if (thermalize) {
                 const Vec3<T> z = Draws<T>::normals(key, i - leaf_end);
                 V.vx[s] = (T)(u0 + a * ((double)z.x - z0));

@@ -69,14 +69,16 @@ struct CellRef {
 __host__ __device__ inline uint64_t coll_cap(uint64_t n) { return 4ull * n + 256ull; }
 __host__ __device__ inline uint64_t align16(uint64_t b) { return (b + 15ull) & ~15ull; }
 
-// Per-cell scratch regions: role[n] u32 | fwd[n] u32 | leaf[3][n] | fin[3][n] |
-// j[cap] u32 | rA[cap] u32 | rB[cap] u32 | out[3][2 cap], with elements of `sz`
-// bytes.  The region of cell c starts at bpp * offset(c) + cpc * c, which never
-// overlaps the next one because its size is at most bpp * n + cpc.
-__host__ __device__ inline uint64_t scratch_bpp(uint32_t sz) { return align16(56ull + 30ull * sz); }
+// Per-cell scratch regions: role[n] u32 | fwd[n] u32 | leaf[n] | fin[n] |
+// j[cap] u32 | rA[cap] u32 | rB[cap] u32 | out[2 cap], where leaf, fin and out
+// hold velocities as 4-component records of `sz`-byte elements (x, y, z, pad;
+// one 16- or 32-byte access per velocity).  The region of cell c starts at
+// bpp * offset(c) + cpc * c, which never overlaps the next one because its size
+// is at most bpp * n + cpc.
+__host__ __device__ inline uint64_t scratch_bpp(uint32_t sz) { return align16(56ull + 40ull * sz); }
 __host__ __device__ inline uint64_t scratch_cpc(uint32_t sz)
 {
-    return ((256ull * (12ull + 6ull * sz) + 195ull + 255ull) / 256ull) * 256ull;
+    return ((256ull * (12ull + 8ull * sz) + 195ull + 255ull) / 256ull) * 256ull;
 }
 
 }  // namespace trmc

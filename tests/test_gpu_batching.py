@@ -147,7 +147,9 @@ def test_autotuner_table_is_valid(trmc):
     table, timings = autotune(insts, parts, warmup=1, steps=1)
     assert len(table) == T.SCHED_BUCKETS
     for b, res in timings.items():
-        assert table[b] == min(res, key=res.get) and all(t > 0 for t in res.values())
+        best = min(res, key=res.get)
+        assert all(t > 0 for t in res.values())
+        assert table[b] == best or (table[b] == T.PATH_GROUP and res[best] > 0.95 * res[T.PATH_GROUP])
     for p, b in zip(parts, before):  # the tuner steps copies only
         assert torch_equal(p["vx"], b)
     ctx = T.Context(insts, parts)
