@@ -160,50 +160,55 @@ static uint64_t iround(double y, double u)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Keyed permutation of [0, n): a 6-round balanced Feistel network on b bits  */
-/* (b the smallest even number >= max(8, ceil(log2 n))) with cycle walking.   */
-/* Round i uses the key word k[i mod 4] xor (i * 0x9E3779B9); the round       */
-/* function is the 32-bit finalizer of MurmurHash3 applied to (R xor key).    */
-/* (A 4-round network on 2-bit halves is visibly non-uniform for tiny n.)     */
+/* Keyed permutation of [0, n): a 6-round alternating Feistel network on b    */
+/* bits, b = max(8, ceil(log2 n)), with cycle walking.  A value is split into */
+/* a high part of ceil(b/2) bits and a low part of floor(b/2) bits; round i   */
+/* xors F(low) into the high part when i is even and F(high) into the low     */
+/* part when i is odd.  Round i uses the key word k[i mod 4] xor              */
+/* (i * 0x9E3779B9); F(x) = mix24(x xor key), where mix24 multiplies the low  */
+/* 24 bits by 0xEBCA6B (keeping the low 32 bits of the product), xors in its  */
+/* value shifted right by 15, multiplies the low 24 bits by 0xB2AE35 and      */
+/* xors in its value shifted right by 13.                                     */
 /* ------------------------------------------------------------------------- */
-static uint32_t fmix32(uint32_t h)
+static uint32_t mul24(uint32_t a, uint32_t b)
 {
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
+    return (uint32_t)(((uint64_t)(a & 0xFFFFFFu) * (uint64_t)(b & 0xFFFFFFu)) & 0xFFFFFFFFull);
+}
+
+static uint32_t mix24(uint32_t x)
+{
+    uint32_t h = mul24(x, 0xEBCA6Bu);
+    h ^= h >> 15;
+    h = mul24(h, 0xB2AE35u);
     h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
     return h;
 }
 
-static uint32_t perm_half_bits(uint32_t n)
+static uint32_t perm_bits(uint32_t n)
 {
     uint32_t b = 0;
     while (b < 32 && ((uint64_t)1 << b) < (uint64_t)n) ++b;
-    if (b < 8) b = 8;
-    if (b & 1u) ++b;
-    return b / 2;
+    return b < 8 ? 8 : b;
 }
 
-static uint32_t feistel_once(uint32_t x, uint32_t half, const uint32_t k[4])
+static uint32_t feistel_once(uint32_t x, uint32_t b, const uint32_t k[4])
 {
-    uint32_t mask = (half >= 32) ? 0xFFFFFFFFu : ((1u << half) - 1u);
-    uint32_t L = x >> half, R = x & mask;
+    uint32_t lo = b / 2, hi = b - lo;
+    uint32_t mlo = (uint32_t)(((uint64_t)1 << lo) - 1u), mhi = (uint32_t)(((uint64_t)1 << hi) - 1u);
+    uint32_t H = x >> lo, W = x & mlo;
     for (uint32_t i = 0; i < 6; ++i) {
         uint32_t rk = k[i & 3u] ^ (i * 0x9E3779B9u);
-        uint32_t nl = R;
-        uint32_t nr = L ^ (fmix32(R ^ rk) & mask);
-        L = nl;
-        R = nr;
+        if ((i & 1u) == 0) H ^= mix24(W ^ rk) & mhi;
+        else W ^= mix24(H ^ rk) & mlo;
     }
-    return (L << half) | R;
+    return (H << lo) | W;
 }
 
 uint32_t orc_perm(uint32_t i, uint32_t n, const uint32_t k[4])
 {
-    uint32_t half = perm_half_bits(n);
-    uint32_t x = feistel_once(i, half, k);
-    while (x >= n) x = feistel_once(x, half, k);
+    uint32_t b = perm_bits(n);
+    uint32_t x = feistel_once(i, b, k);
+    while (x >= n) x = feistel_once(x, b, k);
     return x;
 }
 

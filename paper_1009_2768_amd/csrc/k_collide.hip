@@ -116,7 +116,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     // ---- 1-2. moments, roles, parameters of the step ------------------------
     {
         const uint4 pk = draw(key, 0, TAG_PERM, 0);
-        const uint32_t half = perm_half(n);
+        const uint32_t pbits = perm_bits(n);
         const double c0 = (double)vx[0];  // shift for the one-pass P_xx
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         // loads of the next batch are issued before the current batch's role
@@ -150,7 +150,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
                     s[1] += (double)ay[u];
                     s[2] += (double)az[u];
                     s[3] += dx * dx;
-                    M.role[i] = perm_inverse(i, n, half, pk);
+                    M.role[i] = perm_inverse(i, n, pbits, pk);
                 }
             }
 #pragma unroll

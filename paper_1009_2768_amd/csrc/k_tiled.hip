@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
     const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
     const Key key{V.I->seed, V.I->uid, 0u, V.I->step};
     const uint4 pk = draw(key, 0, TAG_PERM, 0);
-    const uint32_t half = perm_half(n);
+    const uint32_t pbits = perm_bits(n);
     CellMem<T> M;
     M.init(V.I, 0, 0, n);
     uint32_t* role = M.role;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
                 s[1] += (double)ay[u];
                 s[2] += (double)az[u];
                 s[3] += dx * dx;
-                const uint32_t r = perm_inverse(i, n, half, pk);
+                const uint32_t r = perm_inverse(i, n, pbits, pk);
                 role[i] = r;
                 fwd[r] = i;
             }

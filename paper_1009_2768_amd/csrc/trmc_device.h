@@ -146,74 +146,48 @@ __device__ __forceinline__ uint32_t iround_prod(double q, uint32_t rem, double u
 }
 
 // ---------------------------------------------------------------------------
-// Keyed permutation of roles: 6-round balanced Feistel network on b bits,
-// b = smallest even number >= max(8, ceil(log2 n)), cycle walking into [0, n).
-// Round i keys with k[i & 3] ^ (i * 0x9E3779B9); round function = MurmurHash3
-// 32-bit finalizer.  perm_inverse(s) returns the role index of slot s.
+// Keyed permutation of roles: a 6-round alternating Feistel network on b bits,
+// b = max(8, ceil(log2 n)), cycle walking into [0, n).  A value is a high part
+// of ceil(b/2) bits and a low part of floor(b/2) bits; even rounds xor F(low)
+// into the high part, odd rounds F(high) into the low part.  Round i keys with
+// k[i & 3] ^ (i * 0x9E3779B9); F(x) = mix24(x ^ key), a multiply-xorshift
+// finalizer built from 24-bit products (full-rate v_mul_u32_u24).
+// perm_inverse(s) returns the role index of slot s.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+__device__ __forceinline__ uint32_t mix24(uint32_t x)
 {
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
+    uint32_t h = __umul24(x, 0xEBCA6Bu);
+    h ^= h >> 15;
+    h = __umul24(h, 0xB2AE35u);
     h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
     return h;
 }
 
-__device__ __forceinline__ uint32_t perm_half(uint32_t n)
+__device__ __forceinline__ uint32_t perm_bits(uint32_t n)
 {
-    uint32_t b = (n <= 1u) ? 0u : 32u - __clz(n - 1u);  // ceil(log2 n)
-    b = b < 8u ? 8u : b;
-    b += b & 1u;
-    return b >> 1;
+    const uint32_t b = (n <= 1u) ? 0u : 32u - __clz(n - 1u);  // ceil(log2 n)
+    return b < 8u ? 8u : b;
 }
 
-__device__ __forceinline__ uint32_t feistel_dec(uint32_t y, uint32_t half, uint4 k)
+__device__ __forceinline__ uint32_t feistel_dec(uint32_t y, uint32_t b, uint4 k)
 {
-    const uint32_t mask = (half >= 32u) ? 0xFFFFFFFFu : ((1u << half) - 1u);
-    uint32_t L = y >> half, R = y & mask;
+    const uint32_t lo = b >> 1, hi = b - lo;
+    const uint32_t mlo = (1u << lo) - 1u, mhi = (hi >= 32u) ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+    uint32_t H = y >> lo, W = y & mlo;
     const uint32_t kk[4] = {k.x, k.y, k.z, k.w};
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         const uint32_t rk = kk[i & 3] ^ ((uint32_t)i * 0x9E3779B9u);
-        // forward: (L, R) -> (R, L ^ F(R ^ rk)); inverse below
-        const uint32_t pl = R ^ (fmix32(L ^ rk) & mask);
-        const uint32_t pr = L;
-        L = pl;
-        R = pr;
+        if ((i & 1) == 0) H ^= mix24(W ^ rk) & mhi;
+        else W ^= mix24(H ^ rk) & mlo;
     }
-    return (L << half) | R;
+    return (H << lo) | W;
 }
 
-__device__ __forceinline__ uint32_t feistel_enc(uint32_t x, uint32_t half, uint4 k)
+__device__ __forceinline__ uint32_t perm_inverse(uint32_t s, uint32_t n, uint32_t b, uint4 k)
 {
-    const uint32_t mask = (half >= 32u) ? 0xFFFFFFFFu : ((1u << half) - 1u);
-    uint32_t L = x >> half, R = x & mask;
-    const uint32_t kk[4] = {k.x, k.y, k.z, k.w};
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        const uint32_t rk = kk[i & 3] ^ ((uint32_t)i * 0x9E3779B9u);
-        const uint32_t nl = R;
-        const uint32_t nr = L ^ (fmix32(R ^ rk) & mask);
-        L = nl;
-        R = nr;
-    }
-    return (L << half) | R;
-}
-
-// Slot of role index i.
-__device__ __forceinline__ uint32_t perm_forward(uint32_t i, uint32_t n, uint32_t half, uint4 k)
-{
-    uint32_t x = feistel_enc(i, half, k);
-    while (x >= n) x = feistel_enc(x, half, k);
-    return x;
-}
-
-__device__ __forceinline__ uint32_t perm_inverse(uint32_t s, uint32_t n, uint32_t half, uint4 k)
-{
-    uint32_t y = feistel_dec(s, half, k);
-    while (y >= n) y = feistel_dec(y, half, k);
+    uint32_t y = feistel_dec(s, b, k);
+    while (y >= n) y = feistel_dec(y, b, k);
     return y;
 }
 

@@ -103,6 +103,41 @@ def test_perm_positions_uniform(orc, n):
     assert chi2 < stats.chi2.ppf(0.9995, (n - 1) ** 2)
 
 
+@pytest.mark.parametrize("n", [300, 1000, 4097, 70000])
+def test_perm_positions_uniform_in_bins(orc, n):
+    """Larger domains (odd and even bit counts, heavy cycle walking at 4097):
+    element bins against position bins over keys are uniform (chi-square), and
+    the position of an element is uncorrelated with its index."""
+    trials, nb = 400, 8
+    rng = np.random.default_rng(n)
+    idx = rng.choice(n, size=64, replace=False)
+    counts = np.zeros((nb, nb))
+    corr = []
+    for t in range(trials):
+        keys = orc.philox([t, 2 << 24, n, 7], [3, 4])
+        pos = np.array([orc.perm(int(i), n, keys) for i in idx])
+        counts[(idx * nb) // n, (pos * nb) // n] += 1
+        corr.append(np.corrcoef(idx, pos)[0, 1])
+    expect = counts.sum(1, keepdims=True) / nb
+    chi2 = ((counts - expect) ** 2 / expect).sum()
+    assert chi2 < stats.chi2.ppf(0.9995, nb * (nb - 1))
+    # the mean correlation over keys of 64 pairs has standard deviation about 1/sqrt(63 * trials)
+    assert abs(np.mean(corr)) < 5.0 / math.sqrt(63 * trials)
+
+
+def test_perm_kept_set_is_uniform_over_slots(orc):
+    """The unchanged set (the first N0 roles) covers every slot with frequency N0/n."""
+    n, n0, trials = 50, 20, 3000
+    hits = np.zeros(n)
+    for t in range(trials):
+        keys = orc.philox([t, 2 << 24, 5, 9], [1, 1])
+        for r in range(n0):
+            hits[orc.perm(r, n, keys)] += 1
+    p = n0 / n
+    z = (hits - trials * p) / math.sqrt(trials * p * (1 - p))
+    assert np.abs(z).max() < 4.5
+
+
 # ----------------------------------------------------------------------------
 # Alg. 4.2: split into collision sets; eq. (WST-r) coefficients
 # ----------------------------------------------------------------------------
