@@ -220,42 +220,4 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red)
     }
 }
 
-__device__ __forceinline__ double block_max(double v, double* red)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double a = red[0];
-    for (int w = 1; w < nw; ++w) a = fmax(a, red[w]);
-    return a;
-}
-
-template <int K>
-__device__ __forceinline__ void block_sum_u64(unsigned long long (&v)[K], unsigned long long* red)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        unsigned long long a = v[k];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
-        v[k] = a;
-    }
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        unsigned long long a = 0;
-        for (int w = 0; w < nw; ++w) a += red[w * K + k];
-        v[k] = a;
-    }
-}
-
 }  // namespace trmc

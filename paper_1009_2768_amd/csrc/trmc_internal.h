@@ -17,7 +17,10 @@ constexpr uint32_t kSortTile = 4096;     // particles per tile of the counting s
 constexpr uint32_t kTile = 8192;         // slots per tile of the tiled collision pipeline
 constexpr uint32_t kBigStateBytes = 1024; // per-cell state of the tiled pipeline (before its level arrays)
 constexpr uint32_t kRoleBlock = 512;     // roles per block sum of the tiled pipeline
-constexpr uint32_t kCollideThreads = 512;
+#ifndef TRMC_COLLIDE_THREADS
+#define TRMC_COLLIDE_THREADS 512
+#endif
+constexpr uint32_t kCollideThreads = TRMC_COLLIDE_THREADS;  // threads per workgroup of the whole-cell kernel
 constexpr uint32_t kSmallPerBlock = kCollideThreads / 64;  // wave-per-cell groups per workgroup
 constexpr uint32_t kSmallCell = 4096;  // cells expected to hold at most this many particles use one wave
 constexpr uint32_t kSmallDepth = 256;  // ... if their m_cap is at most this
