@@ -276,8 +276,9 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
     const bool thermalize = n_th >= 2;
     if (thermalize) {
-        // normals of thermalized ordinal t = i - leaf_end, written in place into
-        // the slot (unscaled) and summed; the rescale follows in the write-back
+        // sums of the normals of thermalized ordinals t = i - leaf_end; the
+        // write-back draws the same normals again and rescales them (cheaper
+        // than storing and reloading them)
         double zs[4] = {0, 0, 0, 0};
         for (uint32_t s0 = tid; s0 < n; s0 += G * kUnroll) {
             uint32_t ro[kUnroll];
@@ -291,9 +292,6 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
                 const uint32_t s = s0 + u * G;
                 if (s < n && ro[u] >= leaf_end) {
                     const Vec3<T> z = Draws<T>::normals(key, ro[u] - leaf_end);
-                    vx[s] = z.x;
-                    vy[s] = z.y;
-                    vz[s] = z.z;
                     const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
                     zs[0] += zx;
                     zs[1] += zy;
@@ -321,19 +319,15 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const double u0 = sh.ur[0], u1 = sh.ur[1], u2 = sh.ur[2];
         const double z0 = sh.zbar[0], z1 = sh.zbar[1], z2 = sh.zbar[2];
         constexpr int kWU = 2;
-        // loads of a batch are issued before any is used: the roles and current
-        // values, then the finals of the leaf slots (final r of leaf r)
+        // the roles of a batch, then the finals of its leaf slots (final r of
+        // leaf r); thermalized slots draw their normals again
         for (uint32_t s0 = tid; s0 < n; s0 += G * kWU) {
             uint32_t ro[kWU];
-            T fx[kWU], fy[kWU], fz[kWU], cx[kWU], cy[kWU], cz[kWU];
+            T fx[kWU], fy[kWU], fz[kWU];
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {
                 const uint32_t s = s0 + u * G;
-                const bool ok = s < n;
-                ro[u] = ok ? M.role[s] : 0u;
-                cx[u] = ok ? vx[s] : T(0);
-                cy[u] = ok ? vy[s] : T(0);
-                cz[u] = ok ? vz[s] : T(0);
+                ro[u] = s < n ? M.role[s] : 0u;
             }
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {
@@ -355,9 +349,10 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
                     vy[s] = fy[u];
                     vz[s] = fz[u];
                 } else if (thermalize) {
-                    vx[s] = (T)(u0 + a * ((double)cx[u] - z0));
-                    vy[s] = (T)(u1 + a * ((double)cy[u] - z1));
-                    vz[s] = (T)(u2 + a * ((double)cz[u] - z2));
+                    const Vec3<T> z = Draws<T>::normals(key, i - leaf_end);
+                    vx[s] = (T)(u0 + a * ((double)z.x - z0));
+                    vy[s] = (T)(u1 + a * ((double)z.y - z1));
+                    vz[s] = (T)(u2 + a * ((double)z.z - z2));
                 }
             }
         }
