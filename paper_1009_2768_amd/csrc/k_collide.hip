@@ -101,9 +101,8 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     if (n >= TRMC_PRIO_CELL) __builtin_amdgcn_s_setprio(2);
     if (n < 2) {
         if (tid == 0) {
-            CellStats s{};
+            CellStats s{};  // skipped: no attempt, no draws
             s.n = n;
-            s.m_used = I->m_state[cell];
             *st = s;
         }
         return;

@@ -279,9 +279,8 @@ __global__ __launch_bounds__(kTT) void k_big_split(const CellRef* __restrict__ b
             const uint32_t idx = atomicAdd(&cl.count[heavy], 1u);
             cl.list[heavy * cl.cap + idx] = b;
         } else {
-            CellStats s{};
+            CellStats s{};  // skipped: no attempt, no draws
             s.n = n;
-            s.m_used = I->m_state[0];
             *I->stats = s;
         }
     }

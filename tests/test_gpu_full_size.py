@@ -187,3 +187,35 @@ def test_sod_tube_200_cells_200_steps_fp32(trmc):
     assert np.all((got["x"] >= 0) & (got["x"] <= 1))
     assert np.all(mom["status"] == 0)
     assert math.isfinite(float(np.sum(mom["M4"])))
+
+
+def test_largest_serving_request_on_the_tile_path_fp64(trmc, orc):
+    """A homogeneous request at the serving stream's largest size (10^6 particles)
+    on the tile path that the serving schedule picks for it."""
+    T = trmc
+    n = 1_000_000
+    vx, vy, vz = W.bimaxwellian(n, seed=3, stream=4)
+    inst = T.Instance(n_particles=n, eps=0.3, alpha=1.0, trunc=T.ADAPTIVE, m_cap=64, uid=31, seed=3,
+                      precision=T.FP64)
+    say(f"homogeneous fp64 n={n} on the tile path")
+    parts = [T.device_particles(vx, vy, vz, None, T.FP64)]
+    ctx = T.Context([inst], parts)
+    ctx.set_schedule(table_of(T, ",".join(f"{b}:tiled" for b in range(8, 21))))
+    ctx.step(2)
+    got, mom = ctx.read(0), ctx.moments(0)
+    ctx.close()
+    o = oracle_of(orc, inst, {"vx": vx, "vy": vy, "vz": vz})
+    o.run(2)
+    compare(o, got, mom, 1)
+
+
+def test_slab_with_the_most_cells(trmc, orc):
+    """A slab at the cell limit (12288 cells, the LDS histogram of the sort)."""
+    T = trmc
+    nc = 12288
+    inst, a = _tube(T, nc, 12, 2, 0.02, T.FP64, uid=32)
+    say(f"slab fp64 with {nc} cells, {inst.n_particles} particles")
+    got, mom = _run(T, inst, a, 2)
+    o = oracle_of(orc, inst, a)
+    o.run(2)
+    compare(o, got, mom, nc)

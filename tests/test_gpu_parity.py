@@ -144,8 +144,12 @@ def test_small_cells_and_folding(trmc, orc, n):
     for inst, a, (got, mom) in zip(insts, arrays, res):
         o = oracle_of(orc, inst, a)
         o.run(3)
-        if n < 2:
+        if n < 2:  # skipped: unchanged, no attempt, depth kept
             np.testing.assert_array_equal(got["vx"], a["vx"])
+            for gk, ok in INT_FIELDS:
+                o_val = int(o.m_state[0]) if gk == "m_state" else int(getattr(o.last[0], ok))
+                assert int(mom[gk][0]) == o_val, gk
+            assert int(mom["status"][0]) == 0
             continue
         compare(o, got, mom, 1)
 
