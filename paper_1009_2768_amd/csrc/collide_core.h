@@ -237,7 +237,7 @@ __device__ __forceinline__ int collide(const Vec3<T>& a, const Vec3<T>& b, T xi1
 // Scalars shared by a group.
 struct CellShared {
     double mean[3];
-    double Sn, q, g, ur[3], a_th, zbar[3], E1;
+    double Sn, q, g, ur[3], a_th, zbar[3], E1, kept0;
     uint32_t me, split_rem, R0, N0, borrowed, n_th, folds, m, attempts, decision, overflow;
     unsigned long long ncoll, work;
     uint32_t dummies, viol;
@@ -596,14 +596,16 @@ __device__ __forceinline__ uint32_t leaf_role(uint32_t r, uint32_t N0, uint32_t 
 // Leaves and sums of the unchanged and thermalized sets over slots [s_begin,
 // s_end) of a cell with NT threads (this thread's share): leaf r is copied to
 // leaf[r] unless r < r_done (already there from an earlier attempt: the leaf of
-// a rank does not depend on the depth); sums = {kept (vx-m)^2, thermalized
+// a rank does not depend on the depth); with pool_all (no borrowed leaves) the
+// thermalized roles i are copied too, as rank i - N0, so that later attempts
+// find their whole pool in rank order.  sums = {kept (vx-m)^2, thermalized
 // (vx-m)^2, thermalized v-m (3), thermalized |v-m|^2}.  Roles below kept_end
 // are unchanged, roles from leaf_end on are thermalized, the others are leaves.
 template <typename T, int NT>
 __device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* vz, const uint32_t* role, Pack4<T>* leaf,
                                             uint32_t n, uint32_t N0, uint32_t s_begin, uint32_t s_end,
-                                            uint32_t kept_end, uint32_t leaf_end, uint32_t r_done, double mx,
-                                            double my, double mz, uint32_t tid, double (&sums)[6])
+                                            uint32_t kept_end, uint32_t leaf_end, uint32_t r_done, bool pool_all,
+                                            double mx, double my, double mz, uint32_t tid, double (&sums)[6])
 {
     constexpr int U = 4;
     const uint32_t P = n - N0;
@@ -630,6 +632,7 @@ __device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* v
                 const uint32_t r = leaf_rank(i, N0, P);
                 if (r >= r_done) leaf[r] = pack(ax[u], ay[u], az[u]);
             } else {
+                if (pool_all && i - N0 >= r_done) leaf[i - N0] = pack(ax[u], ay[u], az[u]);
                 const double dx = (double)ax[u] - mx, dy = (double)ay[u] - my, dz = (double)az[u] - mz;
                 sums[1] += dx * dx;
                 sums[2] += dx;

@@ -221,7 +221,12 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     const T gT = (T)sh.g;
 
     // ---- 3. attempts ------------------------------------------------------------
+    // A redo keeps the unchanged set when no leaf is borrowed.  The first redo
+    // copies the whole pool (roles from N0 on) in rank order; later redos sum
+    // their thermalized set (ranks R0 .. P of the pool) from that copy.
     uint32_t leaves_done = 0;  // leaf ranks [0, leaves_done) are gathered
+    uint32_t attempt = 0;
+    bool pooled = false;
     for (;;) {
         split_levels<G>(key, n, sh.q, L, sh, tid);
         TRMC_PHASE(1);
@@ -233,9 +238,26 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
         const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
         double sums[6] = {0, 0, 0, 0, 0, 0};
-        gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done, mx, my, mz,
-                          tid, sums);
-        leaves_done = R0 > leaves_done ? R0 : leaves_done;
+        const bool no_borrow = R0 <= P;
+        if (pooled && no_borrow) {
+            for (uint32_t r = R0 + tid; r < P; r += G) {
+                const Vec3<T> v = unpack(M.leaf[r]);
+                const double dx = (double)v.x - mx, dy = (double)v.y - my, dz = (double)v.z - mz;
+                sums[1] += dx * dx;
+                sums[2] += dx;
+                sums[3] += dy;
+                sums[4] += dz;
+                sums[5] += dx * dx + dy * dy + dz * dz;
+            }
+            if (tid == 0) sums[0] = sh.kept0;
+        } else {
+            const bool pool_all = attempt > 0 && no_borrow;
+            gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done, pool_all,
+                              mx, my, mz, tid, sums);
+            leaves_done = pool_all ? P : (R0 > leaves_done ? R0 : leaves_done);
+            pooled = pool_all;
+        }
+        ++attempt;
         gsync<G>();  // leaves visible
         TRMC_PHASE(3);
 
@@ -249,6 +271,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const uint32_t td = gsum_u32<G>(dummies, gl.redu);
         const uint32_t tv = gsum_u32<G>(viol, gl.redu);
         if (tid == 0) {
+            sh.kept0 = all[0];
             sh.dummies = td;
             sh.viol = tv;
             decide(I, cell, n, all, mx, my, mz, sh);
