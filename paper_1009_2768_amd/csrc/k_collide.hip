@@ -65,7 +65,7 @@ __device__ unsigned long long g_maxcell[12];
     } while (0)
 #endif
 
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 2;
 
 template <typename T, int NT, int G>
 __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, uint32_t n_work, uint32_t blk,
