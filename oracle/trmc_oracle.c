@@ -38,9 +38,10 @@
  *       permutation; missing leaves are borrowed from the unchanged block in
  *       reverse order, and if even that is not enough the deepest level is folded
  *       into the remainder;
- *   R7  the Maxwellian remainder is sampled by Box-Muller and then affinely
- *       rescaled to the removed particles' momentum and energy (exact
- *       conservation); a remainder of at most one particle is left unchanged,
+ *   R7  the Maxwellian remainder is sampled by Box-Muller, the sample of a
+ *       thermalized particle keyed by its slot, and then affinely rescaled to
+ *       the removed particles' momentum and energy (exact conservation); a
+ *       remainder of at most one particle is left unchanged,
  *       and a normal sample with zero spread (not reachable in practice) puts
  *       the remainder at the removed mean;
  *   R8  adaptive depth (Sec. 4.3) uses S = P_xx per unit mass, the analytic
@@ -326,7 +327,7 @@ static int collide(vec3 a, vec3 b, double xi1, double xi2, double xacc, double a
     return 1;
 }
 
-/* Three standard normals for thermalized ordinal t (Box-Muller). */
+/* Three standard normals for the thermalized particle in slot t (Box-Muller). */
 static vec3 maxw_normals(const stream_key* s, uint64_t t)
 {
     uint32_t b0[4], b1[4];
@@ -520,7 +521,7 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
             }
             vec3 zm = {0, 0, 0};
             for (uint64_t t = 0; t < ro.n_th; ++t) {
-                wth[t] = maxw_normals(key, t);
+                wth[t] = maxw_normals(key, therm_slot(&ro, t));
                 zm.x += wth[t].x; zm.y += wth[t].y; zm.z += wth[t].z;
             }
             zm.x /= (double)ro.n_th; zm.y /= (double)ro.n_th; zm.z /= (double)ro.n_th;

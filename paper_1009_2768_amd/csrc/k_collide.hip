@@ -298,7 +298,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
     const bool thermalize = n_th >= 2;
     if (thermalize) {
-        // sums of the normals of thermalized ordinals t = i - leaf_end; the
+        // sums of the normals of the thermalized slots (keyed by the slot); the
         // write-back draws the same normals again and rescales them (cheaper
         // than storing and reloading them)
         double zs[4] = {0, 0, 0, 0};
@@ -313,7 +313,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t s = s0 + u * G;
                 if (s < n && ro[u] >= leaf_end) {
-                    const Vec3<T> z = Draws<T>::normals(key, ro[u] - leaf_end);
+                    const Vec3<T> z = Draws<T>::normals(key, s);  // keyed by the slot
                     const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
                     zs[0] += zx;
                     zs[1] += zy;
@@ -371,7 +371,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
                     vy[s] = fy[u];
                     vz[s] = fz[u];
                 } else if (thermalize) {
-                    const Vec3<T> z = Draws<T>::normals(key, i - leaf_end);
+                    const Vec3<T> z = Draws<T>::normals(key, s);
                     vx[s] = (T)(u0 + a * ((double)z.x - z0));
                     vy[s] = (T)(u1 + a * ((double)z.y - z1));
                     vz[s] = (T)(u2 + a * ((double)z.z - z2));

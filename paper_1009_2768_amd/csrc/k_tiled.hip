@@ -12,7 +12,7 @@
 //                  sums, collisions level by level (leaves read through the
 //                  slot of each role), adaptive test (Sec. 4.3); a rejected
 //                  attempt is redone inside
-//   k_tile_zsum    tiles: sums of the Maxwellian normals of the thermalized set
+//   k_tile_zsum    tiles: sums of the Maxwellian normals of the thermalized slots
 //   k_tile_write   tiles: leaves take the finals, thermalized slots the rescaled
 //                  Maxwellian samples (normals drawn again from their keys)
 //
@@ -411,11 +411,17 @@ __global__ __launch_bounds__(kTT) void k_tile_zsum(const CellRef* __restrict__ b
     const BigState* S = big_state(I);
     const uint32_t n_th = S->sh.n_th;
     if (S->sh.overflow || n_th < 2) return;
-    const uint32_t t_begin = k * kTile, t_end = (t_begin + kTile < n_th) ? t_begin + kTile : n_th;
+    const uint32_t n = I->cell_off[1] - I->cell_off[0];
+    const uint32_t N0 = S->sh.N0, R0 = S->sh.R0, P = n - N0;
+    const uint32_t leaf_end = N0 + (R0 < P ? R0 : P);
+    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
     const Key key{I->seed, I->uid, 0u, I->step};
+    CellMem<T> M;
+    M.init(I, 0, 0, n);
     double zs[4] = {0, 0, 0, 0};
-    for (uint32_t t = t_begin + threadIdx.x; t < t_end; t += kTT) {
-        const Vec3<T> z = Draws<T>::normals(key, t);
+    for (uint32_t s = s_begin + threadIdx.x; s < s_end; s += kTT) {
+        if (M.role[s] < leaf_end) continue;
+        const Vec3<T> z = Draws<T>::normals(key, s);  // keyed by the slot
         const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
         zs[0] += zx;
         zs[1] += zy;
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
     const uint32_t kept_end = N0 - S->sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
     __shared__ double par[7];  // a, zbar (3), ur (3)
     if (threadIdx.x == 0 && n_th >= 2) {
-        const uint32_t ntz = (n_th + kTile - 1) / kTile;
+        const uint32_t ntz = (n + kTile - 1) / kTile;
         double z[4] = {0, 0, 0, 0};
         for (uint32_t t = 0; t < ntz; ++t)
             for (int q = 0; q < 4; ++q) z[q] += V.I->tpart[8ull * t + q];
@@ -487,7 +493,7 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
                 V.vy[s] = f.y;
                 V.vz[s] = f.z;
             } else if (thermalize) {
-                const Vec3<T> z = Draws<T>::normals(key, i - leaf_end);
+                const Vec3<T> z = Draws<T>::normals(key, s);
                 V.vx[s] = (T)(u0 + a * ((double)z.x - z0));
                 V.vy[s] = (T)(u1 + a * ((double)z.y - z1));
                 V.vz[s] = (T)(u2 + a * ((double)z.z - z2));
