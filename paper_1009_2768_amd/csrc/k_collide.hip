@@ -216,7 +216,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     }
     TRMC_PHASE(0);
 
-    const double mx = sh.mean[0], my = sh.mean[1], mz = sh.mean[2];
+    const double mx = uni(sh.mean[0]), my = uni(sh.mean[1]), mz = uni(sh.mean[2]);
     const T alpha = (T)I->alpha;
     const T gT = (T)sh.g;
 
@@ -337,9 +337,9 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     }
     TRMC_PHASE(6);
     {
-        const double a = sh.a_th;
-        const double u0 = sh.ur[0], u1 = sh.ur[1], u2 = sh.ur[2];
-        const double z0 = sh.zbar[0], z1 = sh.zbar[1], z2 = sh.zbar[2];
+        const double a = uni(sh.a_th);
+        const double u0 = uni(sh.ur[0]), u1 = uni(sh.ur[1]), u2 = uni(sh.ur[2]);
+        const double z0 = uni(sh.zbar[0]), z1 = uni(sh.zbar[1]), z2 = uni(sh.zbar[2]);
         constexpr int kWU = 2;
         // the roles of a batch, then the finals of its leaf slots (final r of
         // leaf r); thermalized slots draw their normals again
