@@ -39,7 +39,7 @@ def make_batch(n_inst: int, seed: int, scale: float = 1.0):
     return N, eps, alpha, init
 
 
-def build_context(T, N, eps, alpha, init, seed, precision, device="cuda"):
+def build_context(T, N, eps, alpha, init, seed, precision, device="cuda", uids=None):
     import numpy as np
     import torch
 
@@ -51,15 +51,16 @@ def build_context(T, N, eps, alpha, init, seed, precision, device="cuda"):
     vy = torch.empty(total, dtype=dt, device=device)
     vz = torch.empty(total, dtype=dt, device=device)
     insts, parts = [], []
+    uids = list(range(len(N))) if uids is None else [int(u) for u in uids]
     for i in range(len(N)):
-        n = int(N[i])
-        a = W.bkw(n, 0.6, seed, 1000 + i) if init[i] == 0 else W.bimaxwellian(n, seed, 1000 + i)
+        n, uid = int(N[i]), uids[i]
+        a = W.bkw(n, 0.6, seed, 1000 + uid) if init[i] == 0 else W.bimaxwellian(n, seed, 1000 + uid)
         sl = slice(int(offs[i]), int(offs[i + 1]))
         vx[sl].copy_(torch.from_numpy(a[0]))
         vy[sl].copy_(torch.from_numpy(a[1]))
         vz[sl].copy_(torch.from_numpy(a[2]))
         insts.append(T.Instance(n_particles=n, eps=float(eps[i]), alpha=float(alpha[i]), dt=0.05,
-                                trunc=T.ADAPTIVE, m_init=2, m_cap=64, precision=precision, uid=i, seed=seed))
+                                trunc=T.ADAPTIVE, m_init=2, m_cap=64, precision=precision, uid=uid, seed=seed))
         parts.append({"vx": vx[sl], "vy": vy[sl], "vz": vz[sl], "x": None})
     ctx = T.Context(insts, parts)
     return ctx, (vx, vy, vz)
@@ -121,6 +122,42 @@ def cpu_baseline(N, eps, alpha, init, seed, budget_s=15.0):
                       f"{sum(i.n for i in insts)} particles), serial FP64 oracle on one core, {t_used:.1f} s"}
 
 
+def batching_speedup(T, N, eps, alpha, init, seed, prec, table, stride=16, steps=3):
+    """Batched versus one instance at a time on the same sample (every stride-th
+    instance): each instance alone in its own context (the plain one-instance
+    path, a graph per step), then all of them in one context; same schedule,
+    same steps, results identical (per-instance keys)."""
+    import numpy as np
+    import torch
+    idx = np.arange(0, len(N), stride)
+    Ns, es, al, ini = N[idx], eps[idx], alpha[idx], init[idx]
+    ctx, bufs = build_context(T, Ns, es, al, ini, seed, prec, uids=idx)
+    ctx.set_schedule(table)
+    ctx.use_graph(True)
+    ctx.step(1)
+    ctx.sync()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.sync()
+    batched = (time.perf_counter() - t0) / steps
+    ctx.close()
+    alone = 0.0
+    for k in range(len(idx)):
+        c1, _ = build_context(T, Ns[k:k + 1], es[k:k + 1], al[k:k + 1], ini[k:k + 1], seed, prec, uids=idx[k:k + 1])
+        c1.set_schedule(table)
+        c1.use_graph(True)
+        c1.step(1)
+        c1.sync()
+        t0 = time.perf_counter()
+        c1.step(steps)
+        c1.sync()
+        alone += (time.perf_counter() - t0) / steps
+        c1.close()
+    torch.cuda.synchronize()
+    return {"instances": int(len(idx)), "particles": int(Ns.sum()), "one_at_a_time_ms_per_step": alone * 1e3,
+            "batched_ms_per_step": batched * 1e3, "speedup": alone / batched}
+
+
 def serving(T, args):
     """Serving run: a Poisson stream of homogeneous solves and shock tubes (N
     log-uniform in [1e3, 1e6], 50-500 steps, eps log-uniform in [1e-4, 1]) served
@@ -166,6 +203,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the Poisson request stream of the serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--speedup-stride", type=int, default=16,
+                    help="compare batched and one-at-a-time stepping on every n-th instance (0 = skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="HBM budget of the running requests")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB each (HBM counter calibration) and exit")
@@ -267,6 +306,10 @@ def main():
     ctx.close()
     del ctx, bufs
     torch.cuda.empty_cache()
+    if args.speedup_stride > 0:
+        log("batched versus one instance at a time ...")
+        line["batching"] = batching_speedup(T, N, eps, alpha, init, args.seed, prec, table, args.speedup_stride)
+        log(f"batching: {line['batching']}")
     if args.serve_seconds > 0:
         line["serving"] = serving(T, args)
     if not args.no_cpu_baseline:
