@@ -279,16 +279,36 @@ __device__ __forceinline__ Pack4<T> pack(T x, T y, T z)
     return Pack4<T>{x, y, z, T(0)};
 }
 
+// Record load and store through a global pointer (one 16-byte access in FP32).
+template <typename T>
+__device__ __forceinline__ Vec3<T> ld3(gptr<const Pack4<T>> p)
+{
+    return Vec3<T>{p->x, p->y, p->z};
+}
+template <typename T>
+__device__ __forceinline__ Vec3<T> ld3(gptr<Pack4<T>> p)
+{
+    return ld3((gptr<const Pack4<T>>)p);
+}
+template <typename T>
+__device__ __forceinline__ void st3(gptr<Pack4<T>> p, T x, T y, T z)
+{
+    p->x = x;
+    p->y = y;
+    p->z = z;
+    p->w = T(0);
+}
+
 template <typename T>
 struct CellMem {
-    uint32_t* role;  // [n] role index of each slot (inverse of the keyed permutation)
-    uint32_t* fwd;   // [n] slot of each role index (the permutation itself; tile path)
-    Pack4<T>* leaf;  // [n] leaves by leaf rank (whole-cell path)
-    Pack4<T>* fin;   // [n] finals by leaf rank (final r goes to the slot of leaf r)
-    uint32_t* jarr;  // [cap] sub-level choice of each collision
-    uint32_t* rA;    // [cap] rank of request A at level j
-    uint32_t* rB;    // [cap] rank of request B at level l-1-j
-    Pack4<T>* outv;  // [2 cap] outputs taken by requests
+    gptr<uint32_t> role;  // [n] role index of each slot (inverse of the keyed permutation)
+    gptr<uint32_t> fwd;   // [n] slot of each role index (the permutation itself; tile path)
+    gptr<Pack4<T>> leaf;  // [n] leaves by leaf rank (whole-cell path)
+    gptr<Pack4<T>> fin;   // [n] finals by leaf rank (final r goes to the slot of leaf r)
+    gptr<uint32_t> jarr;  // [cap] sub-level choice of each collision
+    gptr<uint32_t> rA;    // [cap] rank of request A at level j
+    gptr<uint32_t> rB;    // [cap] rank of request B at level l-1-j
+    gptr<Pack4<T>> outv;  // [2 cap] outputs taken by requests
     uint64_t cap, ocap;
     __device__ __forceinline__ void init(const InstDev* I, uint32_t off, uint32_t cell, uint32_t n)
     {
@@ -296,21 +316,21 @@ struct CellMem {
         ocap = 2ull * cap;
         // the cell is the same on every lane of the wave: scalar base pointers
         unsigned char* base = uni(I->scratch + I->scratch_bpp * (uint64_t)off + I->scratch_cpc * (uint64_t)cell);
-        role = reinterpret_cast<uint32_t*>(base);
+        role = as_global(reinterpret_cast<uint32_t*>(base));
         base += align16(4ull * n);
-        fwd = reinterpret_cast<uint32_t*>(base);
+        fwd = as_global(reinterpret_cast<uint32_t*>(base));
         base += align16(4ull * n);
-        leaf = reinterpret_cast<Pack4<T>*>(base);
+        leaf = as_global(reinterpret_cast<Pack4<T>*>(base));
         base += sizeof(Pack4<T>) * (uint64_t)n;
-        fin = reinterpret_cast<Pack4<T>*>(base);
+        fin = as_global(reinterpret_cast<Pack4<T>*>(base));
         base += sizeof(Pack4<T>) * (uint64_t)n;
-        jarr = reinterpret_cast<uint32_t*>(base);
+        jarr = as_global(reinterpret_cast<uint32_t*>(base));
         base += align16(4ull * cap);
-        rA = reinterpret_cast<uint32_t*>(base);
+        rA = as_global(reinterpret_cast<uint32_t*>(base));
         base += align16(4ull * cap);
-        rB = reinterpret_cast<uint32_t*>(base);
+        rB = as_global(reinterpret_cast<uint32_t*>(base));
         base += align16(4ull * cap);
-        outv = reinterpret_cast<Pack4<T>*>(base);
+        outv = as_global(reinterpret_cast<Pack4<T>*>(base));
     }
 };
 
@@ -410,7 +430,8 @@ __device__ __forceinline__ void split_levels(const Key& key, uint32_t n, double 
 template <int G>
 __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32_t n, uint64_t cap,
                                                           const Levels& L, GroupLds<G>& gl, CellShared& sh,
-                                                          uint32_t* jarr, uint32_t* rA, uint32_t* rB, uint32_t tid)
+                                                          gptr<uint32_t> jarr, gptr<uint32_t> rA, gptr<uint32_t> rB,
+                                                          uint32_t tid)
 {
     constexpr int NWG = G / 64;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
@@ -602,7 +623,8 @@ __device__ __forceinline__ uint32_t leaf_role(uint32_t r, uint32_t N0, uint32_t 
 // (vx-m)^2, thermalized v-m (3), thermalized |v-m|^2}.  Roles below kept_end
 // are unchanged, roles from leaf_end on are thermalized, the others are leaves.
 template <typename T, int NT>
-__device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* vz, const uint32_t* role, Pack4<T>* leaf,
+__device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, gptr<const T> vz,
+                                            gptr<const uint32_t> role, gptr<Pack4<T>> leaf,
                                             uint32_t n, uint32_t N0, uint32_t s_begin, uint32_t s_end,
                                             uint32_t kept_end, uint32_t leaf_end, uint32_t r_done, bool pool_all,
                                             double mx, double my, double mz, uint32_t tid, double (&sums)[6])
@@ -630,9 +652,9 @@ __device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* v
                 sums[0] += d * d;
             } else if (i < leaf_end) {
                 const uint32_t r = leaf_rank(i, N0, P);
-                if (r >= r_done) leaf[r] = pack(ax[u], ay[u], az[u]);
+                if (r >= r_done) st3(leaf + r, ax[u], ay[u], az[u]);
             } else {
-                if (pool_all && i - N0 >= r_done) leaf[i - N0] = pack(ax[u], ay[u], az[u]);
+                if (pool_all && i - N0 >= r_done) st3(leaf + (i - N0), ax[u], ay[u], az[u]);
                 const double dx = (double)ax[u] - mx, dy = (double)ay[u] - my, dz = (double)az[u] - mz;
                 sums[1] += dx * dx;
                 sums[2] += dx;
@@ -656,7 +678,8 @@ __device__ __forceinline__ void gather_sets(const T* vx, const T* vy, const T* v
 constexpr int kBU = TRMC_BOTTOM_UP_BATCH;  // collisions per thread per batch in bottom_up
 
 template <typename T, int G, bool FromSlots>
-__device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const T* vx, const T* vy, const T* vz,
+__device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const T> vx, gptr<const T> vy,
+                                          gptr<const T> vz,
                                           const Levels& L, const CellShared& sh, const CellMem<T>& M,
                                           unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
                                           uint32_t& dummies, uint32_t& viol, double& sfin)
@@ -685,20 +708,20 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const T* v
                         const uint32_t sl = M.fwd[leaf_role(ra, N0, P)];
                         a[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
                     } else {
-                        a[k] = unpack(M.leaf[ra]);
+                        a[k] = ld3(M.leaf + ra);
                     }
                 } else {
-                    a[k] = unpack(M.outv[(uint64_t)L.outoff[j] + ra]);
+                    a[k] = ld3(M.outv + ((uint64_t)L.outoff[j] + ra));
                 }
                 if (h == 0) {
                     if constexpr (FromSlots) {
                         const uint32_t sl = M.fwd[leaf_role(rb, N0, P)];
                         b[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
                     } else {
-                        b[k] = unpack(M.leaf[rb]);
+                        b[k] = ld3(M.leaf + rb);
                     }
                 } else {
-                    b[k] = unpack(M.outv[(uint64_t)L.outoff[h] + rb]);
+                    b[k] = ld3(M.outv + ((uint64_t)L.outoff[h] + rb));
                 }
             }
 #pragma unroll
@@ -713,10 +736,10 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, const T* v
                 for (int e = 0; e < 2; ++e) {
                     const uint32_t o = 2u * c + (uint32_t)e;
                     if (o < Rl) {
-                        M.outv[(uint64_t)oo + o] = pack(out[e].x, out[e].y, out[e].z);
+                        st3(M.outv + ((uint64_t)oo + o), out[e].x, out[e].y, out[e].z);
                     } else {
                         const uint32_t r = fp + (o - Rl);
-                        M.fin[r] = pack(out[e].x, out[e].y, out[e].z);
+                        st3(M.fin + r, out[e].x, out[e].y, out[e].z);
                         const double d = (double)out[e].x - mx;
                         sfin += d * d;
                     }
@@ -779,7 +802,8 @@ __device__ __forceinline__ void decide(InstDev* I, uint32_t cell, uint32_t n, co
 // the slots fwd[i] of the velocities.  This thread's share in out[5]; the
 // caller reduces over the group.
 template <typename T, int G>
-__device__ __forceinline__ void range_sums(const T* vx, const T* vy, const T* vz, const uint32_t* fwd,
+__device__ __forceinline__ void range_sums(gptr<const T> vx, gptr<const T> vy, gptr<const T> vz,
+                                           gptr<const uint32_t> fwd,
                                            const double* bs, uint32_t lo, uint32_t hi, double mx, double my,
                                            double mz, uint32_t tid, double (&out)[5])
 {
@@ -813,7 +837,8 @@ __device__ __forceinline__ void range_sums(const T* vx, const T* vy, const T* vz
 // Sums of an attempt: all = {kept (vx-m)^2, th (vx-m)^2, th v-m (3), th
 // |v-m|^2, (finals, filled by the caller)}.
 template <typename T, int G>
-__device__ __forceinline__ void attempt_sums(const T* vx, const T* vy, const T* vz, const uint32_t* fwd,
+__device__ __forceinline__ void attempt_sums(gptr<const T> vx, gptr<const T> vy, gptr<const T> vz,
+                                             gptr<const uint32_t> fwd,
                                              const double* bs, uint32_t n, uint32_t kept_end, uint32_t leaf_end,
                                              double mx, double my, double mz, uint32_t tid, double* red,
                                              double (&all)[7])

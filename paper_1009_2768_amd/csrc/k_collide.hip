@@ -87,9 +87,9 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     const uint32_t off = uni(I->cell_off[cell]);
     const uint32_t n = uni(I->cell_off[cell + 1]) - off;
     const uint32_t buf = (uni(I->geometry) == GEOM_SLAB) ? (uni(I->cur) ^ 1u) : 0u;
-    T* __restrict__ vx = uni(reinterpret_cast<T*>(I->vx[buf]) + off);
-    T* __restrict__ vy = uni(reinterpret_cast<T*>(I->vy[buf]) + off);
-    T* __restrict__ vz = uni(reinterpret_cast<T*>(I->vz[buf]) + off);
+    const gptr<T> vx = as_global(uni(reinterpret_cast<T*>(I->vx[buf]) + off));
+    const gptr<T> vy = as_global(uni(reinterpret_cast<T*>(I->vy[buf]) + off));
+    const gptr<T> vz = as_global(uni(reinterpret_cast<T*>(I->vz[buf]) + off));
     CellStats* st = I->stats + cell;
     const Key key = uni(Key{I->seed, I->uid, cell, I->step});
 
@@ -241,7 +241,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const bool no_borrow = R0 <= P;
         if (pooled && no_borrow) {
             for (uint32_t r = R0 + tid; r < P; r += G) {
-                const Vec3<T> v = unpack(M.leaf[r]);
+                const Vec3<T> v = ld3(M.leaf + r);
                 const double dx = (double)v.x - mx, dy = (double)v.y - my, dz = (double)v.z - mz;
                 sums[1] += dx * dx;
                 sums[2] += dx;
@@ -356,7 +356,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
                 const uint32_t i = ro[u];
                 const bool lf = s0 + u * G < n && i >= kept_end && i < leaf_end;
                 const uint32_t r = lf ? leaf_rank(i, N0, P) : 0u;
-                const Pack4<T> f = M.fin[lf ? r : 0u];
+                const Vec3<T> f = ld3(M.fin + (lf ? r : 0u));
                 fx[u] = f.x;
                 fy[u] = f.y;
                 fz[u] = f.z;

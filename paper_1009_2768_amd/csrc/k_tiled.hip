@@ -73,8 +73,8 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
     const uint32_t pbits = perm_bits(n);
     CellMem<T> M;
     M.init(V.I, 0, 0, n);
-    uint32_t* role = M.role;
-    uint32_t* fwd = M.fwd;
+    const gptr<uint32_t> role = M.role;
+    const gptr<uint32_t> fwd = M.fwd;
     const double c0 = (double)V.vx[0];
     constexpr int U = 4;
     double s[4] = {0, 0, 0, 0};
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kTT) void k_tile_bsum(const CellRef* __restrict__ b
     const double mx = mean[0], my = mean[1], mz = mean[2];
     CellMem<T> M;
     M.init(V.I, 0, 0, n);
-    const uint32_t* fwd = M.fwd;
+    const gptr<const uint32_t> fwd = M.fwd;
     const uint32_t r_begin = k * kTile, r_end = (r_begin + kTile < n) ? r_begin + kTile : n;
     double d2max = 0.0;
     for (uint32_t b0 = r_begin; b0 < r_end; b0 += kRoleBlock) {
@@ -349,9 +349,9 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
         return;
     }
     const Key key{I->seed, I->uid, 0u, I->step};
-    const T* vx = uni(reinterpret_cast<const T*>(I->vx[0]));
-    const T* vy = uni(reinterpret_cast<const T*>(I->vy[0]));
-    const T* vz = uni(reinterpret_cast<const T*>(I->vz[0]));
+    const gptr<const T> vx = as_global(uni(reinterpret_cast<const T*>(I->vx[0])));
+    const gptr<const T> vy = as_global(uni(reinterpret_cast<const T*>(I->vy[0])));
+    const gptr<const T> vz = as_global(uni(reinterpret_cast<const T*>(I->vz[0])));
     CellMem<T> M;
     M.init(I, 0, 0, n);
     Levels L = levels_at(lv, lv_stride);
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
             if (s >= s_end || i < kept_end) continue;
             if (i < leaf_end) {
                 const uint32_t r = leaf_rank(i, N0, P);  // final r goes to the slot of leaf r
-                const Pack4<T> f = M.fin[r];
+                const Vec3<T> f = ld3(M.fin + r);
                 V.vx[s] = f.x;
                 V.vy[s] = f.y;
                 V.vz[s] = f.z;

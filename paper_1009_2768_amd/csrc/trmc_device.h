@@ -19,6 +19,17 @@ struct Key {
     uint32_t seed, uid, cell, step;
 };
 
+// Pointers known to address global memory: loads and stores become global_*
+// instructions (scalar base + vector offset, counted by vmcnt only) instead of
+// flat ones, which also count against the LDS wait counter.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p)
+{
+    return (gptr<T>)p;
+}
+
 // Values equal on every lane of a wave, moved to scalar registers (the first
 // active lane's copy): cell indices, sizes, keys and base pointers.
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
