@@ -6,7 +6,8 @@ the C source here is built on its own and loaded through ctypes.
 
 The method follows Trazzi, Pareschi and Wennberg: Sec. 3 (time-relaxed
 splitting and the Wild sum), Alg. 4.2 (split into collision sets), Alg. 4.3 and
-4.4 (recursive collision trees, dummy collisions), Sec. 4.3 (adaptive depth).
+4.4 (recursive collision trees, dummy collisions), Sec. 4.3 (adaptive depth),
+Sec. 4.4 (tree-shape truncation, definitions def:2 and def:3, Alg. 4.6).
 """
 from __future__ import annotations
 
@@ -23,6 +24,7 @@ _LIB = os.path.join(_HERE, "libtrmc_oracle.so")
 
 HOMOG, SLAB = 1, 2
 NATURAL, FIXED, ADAPTIVE = 0, 1, 2
+WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
 
 
 def build() -> str:
@@ -43,6 +45,7 @@ class _Desc(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("trunc", ctypes.c_uint32), ("m_init", ctypes.c_uint32), ("m_cap", ctypes.c_uint32),
         ("delta1", ctypes.c_double), ("delta2", ctypes.c_double),
+        ("wb", ctypes.c_uint32), ("wb_mmax", ctypes.c_uint32),
     ]
 
 
@@ -51,7 +54,7 @@ class CellRecord(ctypes.Structure):
         ("n", ctypes.c_uint32), ("N0", ctypes.c_uint32), ("m_eff", ctypes.c_uint32),
         ("m_used", ctypes.c_uint32), ("attempts", ctypes.c_uint32), ("R0", ctypes.c_uint32),
         ("n_th", ctypes.c_uint32), ("borrowed", ctypes.c_uint32), ("folds", ctypes.c_uint32),
-        ("m_state_after", ctypes.c_uint32),
+        ("m_state_after", ctypes.c_uint32), ("wb_th", ctypes.c_uint32),
         ("collisions", ctypes.c_uint64), ("dummies", ctypes.c_uint64),
         ("violations", ctypes.c_uint64), ("work_collisions", ctypes.c_uint64),
         ("q", ctypes.c_double), ("g", ctypes.c_double), ("E1", ctypes.c_double),
@@ -88,6 +91,11 @@ def lib():
         L.orc_split.restype = ctypes.c_int
         L.orc_collide.argtypes = [P(dbl), P(dbl), dbl, dbl, dbl, dbl, dbl, P(dbl), P(dbl)]
         L.orc_collide.restype = ctypes.c_int
+        L.orc_tree.argtypes = [u32, u32, u32, u32, u32, dbl, u32, u32, P(u64), P(u64), P(u64), P(u32),
+                               P(u64), P(u64), u64, P(dbl), P(u32), P(u64)]
+        L.orc_tree.restype = ctypes.c_int64
+        L.orc_wb_len.argtypes = [dbl, dbl, u32]
+        L.orc_wb_len.restype = dbl
         _lib = L
     return _lib
 
@@ -142,6 +150,35 @@ def collide(a, b, xi1, xi2, xacc=0.0, alpha=0.0, g=1.0):
     return oa, ob, bool(acc)
 
 
+def wb_len(a: float, b: float, kind: int) -> float:
+    """Length of a collision's output from its inputs' lengths (Sec. 4.4)."""
+    return lib().orc_wb_len(float(a), float(b), int(kind))
+
+
+def tree(seed, uid, cell, step, n, q, m, kind=WB_OFF, cap=1 << 22):
+    """Tree schedule of one cell (level order) and the lengths of its finals.
+
+    Returns a dict: me, R0, R/C/first per level, j/rA/rB per collision and, for
+    kind WB_MIN or WB_MEAN, finlen (finals listed level 1 first, by output rank)."""
+    R = np.zeros(m + 2, dtype=np.uint64)
+    C = np.zeros(m + 2, dtype=np.uint64)
+    first = np.zeros(m + 2, dtype=np.uint64)
+    j = np.zeros(cap, dtype=np.uint32)
+    rA = np.zeros(cap, dtype=np.uint64)
+    rB = np.zeros(cap, dtype=np.uint64)
+    finlen = np.zeros(max(n, 1))
+    me = ctypes.c_uint32(0)
+    R0 = ctypes.c_uint64(0)
+    nc = lib().orc_tree(seed, uid, cell, step, n, float(q), m, kind, _p(R, ctypes.c_uint64),
+                        _p(C, ctypes.c_uint64), _p(first, ctypes.c_uint64), _p(j, ctypes.c_uint32),
+                        _p(rA, ctypes.c_uint64), _p(rB, ctypes.c_uint64), cap, _p(finlen, ctypes.c_double),
+                        ctypes.byref(me), ctypes.byref(R0))
+    if nc < 0:
+        raise ValueError("tree larger than cap")
+    return {"me": me.value, "R0": R0.value, "R": R, "C": C, "first": first, "j": j[:nc], "rA": rA[:nc],
+            "rB": rB[:nc], "finlen": finlen[:R0.value] if kind != WB_OFF else None}
+
+
 @dataclass
 class Instance:
     """State and parameters of one homogeneous solve or one 1-D slab."""
@@ -164,6 +201,8 @@ class Instance:
     m_cap: int = 64
     delta1: float = 0.005
     delta2: float = 0.01
+    wb: int = WB_OFF
+    wb_mmax: int = 5
     step: int = 0
     m_state: np.ndarray | None = None
     last: list | None = None
@@ -194,6 +233,7 @@ class Instance:
         d.alpha = self.alpha
         d.trunc, d.m_init, d.m_cap = self.trunc, self.m_init, self.m_cap
         d.delta1, d.delta2 = self.delta1, self.delta2
+        d.wb, d.wb_mmax = self.wb, self.wb_mmax
         return d
 
     def run(self, n_steps: int = 1):

@@ -49,7 +49,19 @@
  *       delta1, keeping between delta1 and delta2, and recomputing from the
  *       pre-step velocities at twice the depth above delta2 (same keyed draws);
  *   R9  transport (1-D slab, specular walls) then a stable counting sort by cell,
- *       then the collision step (first-order splitting of Sec. 3.1).
+ *       then the collision step (first-order splitting of Sec. 3.1);
+ *   R15 tree-shape truncation (Sec. 4.4, TRMC-WB of Alg. 4.6): a leaf has length
+ *       0 and both outputs of a collision whose inputs have lengths a and b have
+ *       length 1 + min(a, b) (definition def:2) or 1 + (a + b)/2 (def:3), the
+ *       latter in double as fl(fl(a + b) * 0.5) + 1; the lengths depend on the
+ *       tree schedule only, so they are known before any collision.  A final
+ *       sample whose length exceeds m_max is thermalized: its slot joins the
+ *       Maxwellian remainder of R7.  Every scheduled collision is still
+ *       evaluated (twins make trees share collisions), and the dropped final
+ *       joins the removed set whose momentum and energy the rescale keeps, so
+ *       the step stays conservative.  Twin outputs share a length, so they are
+ *       thermalized together.  Not combined with the adaptive depth (the
+ *       paper leaves that combination open).
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) with
  * key {seed, uid} and counter {index, tag<<24 | aux, cell, step}.
@@ -372,9 +384,39 @@ typedef struct {
     int trunc;
     uint32_t m_init, m_cap;
     double delta1, delta2;
+    uint32_t wb, wb_mmax; /* tree-shape truncation (reading R15): ORC_WB_* and m_max */
 } cell_params;
 
 /* One collision step of one cell, in place on v[0..n). */
+/* Length of a sample made by one collision from inputs of lengths a and b
+ * (Sec. 4.4): definition def:2 (ORC_WB_MIN) or def:3 (ORC_WB_MEAN). */
+static double wb_len(double a, double b, uint32_t kind)
+{
+    if (kind == ORC_WB_MIN) return 1.0 + (a < b ? a : b);
+    return (a + b) * 0.5 + 1.0;
+}
+
+/* Lengths of the final samples of a built tree (reading R15), in the order in
+ * which the collision loop below lists the finals: level 1 first, within a
+ * level by output rank.  lens[l] holds the lengths of level l's outputs. */
+static void tree_lengths(const tree_t* t, uint32_t kind, double** lens, double* finlen)
+{
+    uint64_t nf = 0;
+    for (uint32_t l = 1; l <= t->me; ++l) {
+        lens[l] = xrealloc(lens[l], sizeof(double) * (size_t)(2 * t->C[l] + 1));
+        for (uint64_t c = 0; c < t->C[l]; ++c) {
+            uint64_t id = t->first[l] + c;
+            uint32_t j = t->jch[id], h = l - 1 - j;
+            double a = (j == 0) ? 0.0 : lens[j][t->rA[id]];
+            double b = (h == 0) ? 0.0 : lens[h][t->rB[id]];
+            double L = wb_len(a, b, kind);
+            lens[l][2 * c] = L;
+            lens[l][2 * c + 1] = L;
+        }
+        for (uint64_t o = t->R[l]; o < 2 * t->C[l]; ++o) finlen[nf++] = lens[l][o];
+    }
+}
+
 static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_state, orc_cell_record* rec)
 {
     memset(rec, 0, sizeof *rec);
@@ -431,9 +473,17 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
     vec3* fin = malloc(sizeof(vec3) * n);
     vec3* wth = malloc(sizeof(vec3) * n);
     vec3** out = calloc(cap_levels, sizeof *out);
-    if (!T.N || !T.R || !T.C || !T.first || !T.F || !leaf || !fin || !wth || !out) abort();
+    double** lens = calloc(cap_levels, sizeof *lens);
+    double* finlen = malloc(sizeof(double) * n);
+    uint8_t* wbth = malloc(n);
+    uint32_t* thslot = malloc(sizeof(uint32_t) * n);
+    vec3* thv = malloc(sizeof(vec3) * n);
+    if (!T.N || !T.R || !T.C || !T.first || !T.F || !leaf || !fin || !wth || !out || !lens || !finlen || !wbth ||
+        !thslot || !thv)
+        abort();
 
     uint64_t work_coll = 0;
+    uint64_t nth_acc = 0; /* thermalized slots of the accepted attempt */
     uint32_t attempts = 0;
     roles_t ro;
     uint64_t dummies = 0, viol = 0;
@@ -475,6 +525,16 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         ro.n_th = T.R0 < ro.P ? ro.P - T.R0 : 0;
         memcpy(ro.pk, pk, sizeof pk);
 
+        /* Tree-shape truncation (reading R15): finals whose tree is longer than
+         * m_max are thermalized; the decision needs the schedule only. */
+        uint64_t n_wb = 0;
+        memset(wbth, 0, n);
+        if (cp->wb != ORC_WB_OFF) {
+            tree_lengths(&T, cp->wb, lens, finlen);
+            for (uint64_t r = 0; r < T.R0; ++r)
+                if (finlen[r] > (double)cp->wb_mmax) { wbth[r] = 1; n_wb++; }
+        }
+
         /* Leaves: initial-density samples, i.e. the particles' current velocities. */
         for (uint64_t r = 0; r < T.R0; ++r) leaf[r] = v[leaf_slot(&ro, r)];
 
@@ -505,33 +565,46 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         if (nf != T.R0) abort();
         work_coll += T.ncoll;
 
-        /* Maxwellian remainder (reading R7). */
+        /* Maxwellian remainder (reading R7) over the thermalized slots: the
+         * split's remainder, then the finals thermalized by tree shape (R15).
+         * The removed velocities are the remainder's pre-step ones and the
+         * dropped finals, so the rescale keeps the cell's momentum and energy. */
+        uint64_t nth = 0;
+        for (uint64_t t = 0; t < ro.n_th; ++t) {
+            thslot[nth] = therm_slot(&ro, t);
+            thv[nth++] = v[therm_slot(&ro, t)];
+        }
+        for (uint64_t r = 0; r < T.R0; ++r)
+            if (wbth[r]) {
+                thslot[nth] = leaf_slot(&ro, r);
+                thv[nth++] = fin[r];
+            }
         vec3 ur = {0, 0, 0};
         double Eth = 0.0;
-        if (ro.n_th >= 2) {
-            for (uint64_t t = 0; t < ro.n_th; ++t) {
-                vec3 a = v[therm_slot(&ro, t)];
+        if (nth >= 2) {
+            for (uint64_t t = 0; t < nth; ++t) {
+                vec3 a = thv[t];
                 ur.x += a.x; ur.y += a.y; ur.z += a.z;
             }
-            ur.x /= (double)ro.n_th; ur.y /= (double)ro.n_th; ur.z /= (double)ro.n_th;
-            for (uint64_t t = 0; t < ro.n_th; ++t) {
-                vec3 a = v[therm_slot(&ro, t)];
+            ur.x /= (double)nth; ur.y /= (double)nth; ur.z /= (double)nth;
+            for (uint64_t t = 0; t < nth; ++t) {
+                vec3 a = thv[t];
                 double dx = a.x - ur.x, dy = a.y - ur.y, dz = a.z - ur.z;
                 Eth += dx * dx + dy * dy + dz * dz;
             }
             vec3 zm = {0, 0, 0};
-            for (uint64_t t = 0; t < ro.n_th; ++t) {
-                wth[t] = maxw_normals(key, therm_slot(&ro, t));
+            for (uint64_t t = 0; t < nth; ++t) {
+                wth[t] = maxw_normals(key, thslot[t]);
                 zm.x += wth[t].x; zm.y += wth[t].y; zm.z += wth[t].z;
             }
-            zm.x /= (double)ro.n_th; zm.y /= (double)ro.n_th; zm.z /= (double)ro.n_th;
+            zm.x /= (double)nth; zm.y /= (double)nth; zm.z /= (double)nth;
             double Z = 0.0;
-            for (uint64_t t = 0; t < ro.n_th; ++t) {
+            for (uint64_t t = 0; t < nth; ++t) {
                 double dx = wth[t].x - zm.x, dy = wth[t].y - zm.y, dz = wth[t].z - zm.z;
                 Z += dx * dx + dy * dy + dz * dz;
             }
             double a = Z > 0.0 ? sqrt(Eth / Z) : 0.0;
-            for (uint64_t t = 0; t < ro.n_th; ++t) {
+            for (uint64_t t = 0; t < nth; ++t) {
                 if (Z > 0.0) {
                     wth[t].x = ur.x + a * (wth[t].x - zm.x);
                     wth[t].y = ur.y + a * (wth[t].y - zm.y);
@@ -541,14 +614,16 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
                 }
             }
         } else {
-            for (uint64_t t = 0; t < ro.n_th; ++t) wth[t] = v[therm_slot(&ro, t)];
+            for (uint64_t t = 0; t < nth; ++t) wth[t] = thv[t];
         }
 
         rec->N0 = (uint32_t)N0;
         rec->m_eff = T.me;
         rec->m_used = m;
         rec->R0 = (uint32_t)T.R0;
-        rec->n_th = (uint32_t)ro.n_th;
+        nth_acc = nth;
+        rec->n_th = (uint32_t)nth;
+        rec->wb_th = (uint32_t)n_wb;
         rec->borrowed = (uint32_t)ro.borrowed;
         rec->folds = folds;
         rec->collisions = T.ncoll;
@@ -589,15 +664,16 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
 
     /* Write the accepted result: leaf slots take the finals, thermalized slots
      * take the rescaled Maxwellian samples, the rest are unchanged. */
-    for (uint64_t r = 0; r < ro.R0; ++r) v[leaf_slot(&ro, r)] = fin[r];
-    for (uint64_t t = 0; t < ro.n_th; ++t) v[therm_slot(&ro, t)] = wth[t];
+    for (uint64_t r = 0; r < ro.R0; ++r)
+        if (!wbth[r]) v[leaf_slot(&ro, r)] = fin[r];
+    for (uint64_t t = 0; t < nth_acc; ++t) v[thslot[t]] = wth[t];
 
     rec->attempts = attempts;
     rec->work_collisions = work_coll;
     rec->m_state_after = *m_state;
 
-    for (size_t l = 0; l < cap_levels; ++l) free(out[l]);
-    free(out); free(leaf); free(fin); free(wth);
+    for (size_t l = 0; l < cap_levels; ++l) { free(out[l]); free(lens[l]); }
+    free(out); free(lens); free(finlen); free(wbth); free(thslot); free(thv); free(leaf); free(fin); free(wth);
     free(T.N); free(T.R); free(T.C); free(T.first); free(T.F);
     free(T.jch); free(T.rA); free(T.rB);
 }
@@ -635,6 +711,7 @@ int orc_run(const orc_desc* d, uint64_t n, double* x, double* vx, double* vy, do
     uint32_t nc = d->geometry == ORC_SLAB ? d->n_cells : 1u;
     if (nc == 0) return -1;
     if (d->geometry == ORC_SLAB && !x) return -1;
+    if (d->wb > ORC_WB_MEAN || (d->wb != ORC_WB_OFF && (d->trunc == ORC_ADAPTIVE || d->wb_mmax < 1))) return -1;
     double volume = d->geometry == ORC_SLAB ? d->length / (double)nc : d->length;
     double rho_factor = d->weight / volume;
 
@@ -670,7 +747,8 @@ int orc_run(const orc_desc* d, uint64_t n, double* x, double* vx, double* vy, do
             uint64_t off = start[c], cnt = start[c + 1] - start[c];
             stream_key key = {d->seed, d->uid, c, step};
             cell_params cp = {&key, rho_factor, d->dt, d->eps_cells ? d->eps_cells[c] : d->eps,
-                              d->alpha, d->trunc, d->m_init, d->m_cap, d->delta1, d->delta2};
+                              d->alpha, d->trunc, d->m_init, d->m_cap, d->delta1, d->delta2,
+                              d->wb, d->wb_mmax};
             for (uint64_t i = 0; i < cnt; ++i) {
                 cv[i].x = vx[off + i]; cv[i].y = vy[off + i]; cv[i].z = vz[off + i];
             }
@@ -744,4 +822,56 @@ int orc_collide(const double a[3], const double b[3], double xi1, double xi2, do
     oa[0] = OA.x; oa[1] = OA.y; oa[2] = OA.z;
     ob[0] = OB.x; ob[1] = OB.y; ob[2] = OB.z;
     return acc;
+}
+
+/* Test hook: the tree schedule of one cell for given n, q, m (reading R5) and
+ * the lengths of its finals (reading R15; kind ORC_WB_MIN or ORC_WB_MEAN).
+ * Arrays: R, C, first [m+2]; jch, rA, rB [cap_coll]; finlen [n].  Returns the
+ * number of collisions, or -1 if cap_coll is too small. */
+int64_t orc_tree(uint32_t seed, uint32_t uid, uint32_t cell, uint32_t step, uint32_t n, double q, uint32_t m,
+                 uint32_t kind, uint64_t* R, uint64_t* C, uint64_t* first, uint32_t* jch, uint64_t* rA,
+                 uint64_t* rB, uint64_t cap_coll, double* finlen, uint32_t* me_out, uint64_t* R0_out)
+{
+    stream_key key = {seed, uid, cell, step};
+    size_t cap_levels = (size_t)m + 2;
+    tree_t T;
+    memset(&T, 0, sizeof T);
+    T.N = calloc(cap_levels, sizeof *T.N);
+    T.R = calloc(cap_levels, sizeof *T.R);
+    T.C = calloc(cap_levels, sizeof *T.C);
+    T.first = calloc(cap_levels, sizeof *T.first);
+    T.F = calloc(cap_levels, sizeof *T.F);
+    double** lens = calloc(cap_levels, sizeof *lens);
+    if (!T.N || !T.R || !T.C || !T.first || !T.F || !lens) abort();
+    uint32_t me = 0;
+    orc_split(seed, uid, cell, step, n, q, m, T.N, &me);
+    T.me = me;
+    for (;;) {
+        tree_build(&T, &key);
+        if (T.R0 <= n) break;
+        T.N[T.me] += T.N[T.me + 1];
+        T.me -= 1;
+    }
+    int64_t rc = (int64_t)T.ncoll;
+    if (T.ncoll > cap_coll) {
+        rc = -1;
+    } else {
+        for (uint32_t l = 0; l <= T.me; ++l) { R[l] = T.R[l]; C[l] = T.C[l]; first[l] = T.first[l]; }
+        memcpy(jch, T.jch, sizeof(uint32_t) * T.ncoll);
+        memcpy(rA, T.rA, sizeof(uint64_t) * T.ncoll);
+        memcpy(rB, T.rB, sizeof(uint64_t) * T.ncoll);
+        if (kind != ORC_WB_OFF) tree_lengths(&T, kind, lens, finlen);
+        *me_out = T.me;
+        *R0_out = T.R0;
+    }
+    for (size_t l = 0; l < cap_levels; ++l) free(lens[l]);
+    free(lens); free(T.N); free(T.R); free(T.C); free(T.first); free(T.F);
+    free(T.jch); free(T.rA); free(T.rB);
+    return rc;
+}
+
+/* Test hook: the length rule of Sec. 4.4 for one collision. */
+double orc_wb_len(double a, double b, uint32_t kind)
+{
+    return wb_len(a, b, kind);
 }

@@ -8,6 +8,7 @@
 
 enum { ORC_HOMOG = 1, ORC_SLAB = 2 };
 enum { ORC_NATURAL = 0, ORC_FIXED = 1, ORC_ADAPTIVE = 2 };
+enum { ORC_WB_OFF = 0, ORC_WB_MIN = 1, ORC_WB_MEAN = 2 }; /* tree-shape truncation, Sec. 4.4 */
 
 typedef struct {
     uint32_t seed, uid;
@@ -21,10 +22,13 @@ typedef struct {
     double alpha;        /* VHS exponent: 0 Maxwell molecules, 1 hard spheres */
     uint32_t trunc, m_init, m_cap;
     double delta1, delta2;
+    uint32_t wb;         /* ORC_WB_OFF, or thermalize finals longer than wb_mmax under def:2 / def:3 */
+    uint32_t wb_mmax;
 } orc_desc;
 
 typedef struct {
     uint32_t n, N0, m_eff, m_used, attempts, R0, n_th, borrowed, folds, m_state_after;
+    uint32_t wb_th;      /* finals thermalized by tree shape (included in n_th) */
     uint64_t collisions, dummies, violations, work_collisions;
     double q, g, E1;
 } orc_cell_record;
@@ -41,6 +45,10 @@ void orc_moments(uint64_t n, const double* vx, const double* vy, const double* v
                  double out[9]);
 int orc_split(uint32_t seed, uint32_t uid, uint32_t cell, uint32_t step, uint32_t n, double q, uint32_t m,
               uint64_t* N_out, uint32_t* m_eff_out);
+int64_t orc_tree(uint32_t seed, uint32_t uid, uint32_t cell, uint32_t step, uint32_t n, double q, uint32_t m,
+                 uint32_t kind, uint64_t* R, uint64_t* C, uint64_t* first, uint32_t* jch, uint64_t* rA,
+                 uint64_t* rB, uint64_t cap_coll, double* finlen, uint32_t* me_out, uint64_t* R0_out);
+double orc_wb_len(double a, double b, uint32_t kind);
 int orc_collide(const double a[3], const double b[3], double xi1, double xi2, double xacc, double alpha,
                 double g, double oa[3], double ob[3]);
 
