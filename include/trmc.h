@@ -52,6 +52,11 @@ extern "C" {
 #define TRMC_NATURAL 0  /* depth limited only by m_cap */
 #define TRMC_FIXED 1    /* depth m_init every step */
 #define TRMC_ADAPTIVE 2 /* depth adapted per cell from m_init (Sec. 4.3) */
+/* tree-shape truncation (Sec. 4.4, TRMC-WB of Alg. 4.6): a final sample whose
+   collision tree is longer than wb_mmax is replaced by a Maxwellian sample */
+#define TRMC_WB_OFF 0  /* off */
+#define TRMC_WB_MIN 1  /* length 1 + min of the two subtrees' lengths (definition def:2) */
+#define TRMC_WB_MEAN 2 /* length 1 + mean of the two subtrees' lengths (definition def:3) */
 
 typedef struct trmc_ctx trmc_ctx;
 
@@ -76,6 +81,8 @@ typedef struct trmc_desc {
     uint32_t step0;         /* index of the first step (restart from a saved state) */
     double delta1, delta2;  /* adaptive thresholds, 0 < delta1 < delta2 (Sec. 4.3) */
     const uint32_t* m_state0; /* host [n_cells] saved adaptive depths, or NULL (use m_init) */
+    uint32_t wb;            /* TRMC_WB_OFF / TRMC_WB_MIN / TRMC_WB_MEAN; not with TRMC_ADAPTIVE */
+    uint32_t wb_mmax;       /* m_max of the tree-shape truncation, >= 1 */
 } trmc_desc;
 
 /* Caller-owned device arrays of one instance, SoA, n_particles elements each, of
@@ -107,6 +114,8 @@ typedef struct trmc_cell_moments {
     uint32_t N0;           /* particles kept unchanged by the split */
     uint32_t R0;           /* leaves (initial-density samples) used by the trees */
     uint32_t status;       /* 0, or TRMC_CELL_* flags */
+    uint32_t wb_thermalized; /* finals replaced by tree shape (included in thermalized) */
+    uint32_t reserved;
     double q;              /* exp(-mu dt / eps) = 1 - tau */
     double g;              /* majorant (2 dv)^alpha on the 20-bit grid */
 } trmc_cell_moments;

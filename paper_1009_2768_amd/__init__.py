@@ -17,11 +17,11 @@ import numpy as np
 
 from . import _abi
 from ._abi import (ADAPTIVE, FIXED, FP32_MIXED, FP64, HOMOG, NATURAL, PATH_DEFAULT, PATH_GROUP, PATH_TILED,
-                   PATH_WAVE, SCHED_BUCKETS, SLAB1D, TrmcError, check)
+                   PATH_WAVE, SCHED_BUCKETS, SLAB1D, WB_MEAN, WB_MIN, WB_OFF, TrmcError, check)
 
 __all__ = ["Instance", "Context", "HOMOG", "SLAB1D", "FP64", "FP32_MIXED", "NATURAL", "FIXED", "ADAPTIVE",
-           "PATH_DEFAULT", "PATH_GROUP", "PATH_WAVE", "PATH_TILED", "SCHED_BUCKETS", "TrmcError", "load",
-           "size_bucket"]
+           "PATH_DEFAULT", "PATH_GROUP", "PATH_WAVE", "PATH_TILED", "SCHED_BUCKETS", "WB_OFF", "WB_MIN",
+           "WB_MEAN", "TrmcError", "load", "size_bucket"]
 
 load = _abi.load
 
@@ -48,6 +48,8 @@ class Instance:
     delta1: float = 0.005
     delta2: float = 0.01
     m_state0: np.ndarray | None = None
+    wb: int = WB_OFF  # tree-shape truncation (Sec. 4.4): WB_MIN (def:2) or WB_MEAN (def:3)
+    wb_mmax: int = 5
     _keep: list = field(default_factory=list, repr=False)
 
     def to_c(self) -> _abi.Desc:
@@ -63,6 +65,7 @@ class Instance:
         d.eps, d.alpha = self.eps, self.alpha
         d.trunc, d.m_init, d.m_cap, d.step0 = self.trunc, self.m_init, self.m_cap, self.step0
         d.delta1, d.delta2 = self.delta1, self.delta2
+        d.wb, d.wb_mmax = self.wb, self.wb_mmax
         self._keep = []
         if self.eps_cells is not None:
             e = np.ascontiguousarray(self.eps_cells, dtype=np.float64)

@@ -9,6 +9,7 @@ from . import build as _build
 HOMOG, SLAB1D = 1, 2
 FP64, FP32_MIXED = 1, 2
 NATURAL, FIXED, ADAPTIVE = 0, 1, 2
+WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
 
 EINVAL, ENOMEM, ENOSPC, EIO, EOVERFLOW = -22, -12, -28, -5, -75
 CELL_OVERFLOW = 1
@@ -33,6 +34,7 @@ class Desc(ctypes.Structure):
         ("trunc", ctypes.c_uint32), ("m_init", ctypes.c_uint32), ("m_cap", ctypes.c_uint32),
         ("step0", ctypes.c_uint32), ("delta1", ctypes.c_double), ("delta2", ctypes.c_double),
         ("m_state0", ctypes.POINTER(ctypes.c_uint32)),
+        ("wb", ctypes.c_uint32), ("wb_mmax", ctypes.c_uint32),
     ]
 
 
@@ -51,7 +53,8 @@ class CellMoments(ctypes.Structure):
         ("work_collisions", ctypes.c_uint64),
         ("thermalized", ctypes.c_uint32), ("borrowed", ctypes.c_uint32), ("m_eff", ctypes.c_uint32),
         ("m_used", ctypes.c_uint32), ("attempts", ctypes.c_uint32), ("N0", ctypes.c_uint32),
-        ("R0", ctypes.c_uint32), ("status", ctypes.c_uint32), ("q", ctypes.c_double), ("g", ctypes.c_double),
+        ("R0", ctypes.c_uint32), ("status", ctypes.c_uint32), ("wb_thermalized", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32), ("q", ctypes.c_double), ("g", ctypes.c_double),
     ]
 
 

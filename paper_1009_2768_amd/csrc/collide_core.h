@@ -238,7 +238,8 @@ __device__ __forceinline__ int collide(const Vec3<T>& a, const Vec3<T>& b, T xi1
 struct CellShared {
     double mean[3];
     double Sn, q, g, ur[3], a_th, zbar[3], E1, kept0;
-    uint32_t me, split_rem, R0, N0, borrowed, n_th, folds, m, attempts, decision, overflow;
+    double rs[4];  // tree-shape truncation: split remainder's sums of v - mean (3) and |v - mean|^2
+    uint32_t me, split_rem, R0, N0, borrowed, n_th, folds, m, attempts, decision, overflow, wb_th;
     unsigned long long ncoll, work;
     uint32_t dummies, viol;
 };
@@ -289,6 +290,24 @@ template <typename T>
 __device__ __forceinline__ Vec3<T> ld3(gptr<Pack4<T>> p)
 {
     return ld3((gptr<const Pack4<T>>)p);
+}
+template <typename T>
+__device__ __forceinline__ Pack4<T> ld4(gptr<const Pack4<T>> p)
+{
+    return Pack4<T>{p->x, p->y, p->z, p->w};
+}
+template <typename T>
+__device__ __forceinline__ Pack4<T> ld4(gptr<Pack4<T>> p)
+{
+    return ld4((gptr<const Pack4<T>>)p);
+}
+template <typename T>
+__device__ __forceinline__ void st4(gptr<Pack4<T>> p, T x, T y, T z, T w)
+{
+    p->x = x;
+    p->y = y;
+    p->z = z;
+    p->w = w;
 }
 template <typename T>
 __device__ __forceinline__ void st3(gptr<Pack4<T>> p, T x, T y, T z)
@@ -379,6 +398,7 @@ __device__ __forceinline__ void cell_params(const InstDev* I, uint32_t cell, uin
     sh.attempts = 0;
     sh.work = 0;
     sh.overflow = 0;
+    sh.wb_th = 0;
 }
 
 // a. Split into collision sets (Alg. 4.2) at depth sh.m: wave 0 of the group
@@ -677,12 +697,12 @@ __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, 
 #endif
 constexpr int kBU = TRMC_BOTTOM_UP_BATCH;  // collisions per thread per batch in bottom_up
 
-template <typename T, int G, bool FromSlots>
+template <typename T, int G, bool FromSlots, bool WB = false>
 __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const T> vx, gptr<const T> vy,
                                           gptr<const T> vz,
                                           const Levels& L, const CellShared& sh, const CellMem<T>& M,
                                           unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
-                                          uint32_t& dummies, uint32_t& viol, double& sfin)
+                                          uint32_t& dummies, uint32_t& viol, double& sfin, uint32_t wbk = 0)
 {
     const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
     unsigned long long above = ncoll;  // collisions of deeper levels precede level l's
@@ -697,12 +717,14 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
         // is issued before the first collision is computed
         for (uint32_t c0 = tid; c0 < Cl; c0 += G * kBU) {
             Vec3<T> a[kBU], b[kBU];
+            T len[kBU];  // tree-shape truncation: length of the collision's outputs
 #pragma unroll
             for (int k = 0; k < kBU; ++k) {
                 const uint32_t c = c0 + (uint32_t)k * G;
                 const uint32_t id = fst + (c < Cl ? c : 0u);  // collision 0 stands in past the end
                 const uint32_t j = M.jarr[id], h = l - 1u - j;
                 const uint32_t ra = M.rA[id], rb = M.rB[id];
+                T la = T(0), lb = T(0);  // a leaf has length 0
                 if (j == 0) {
                     if constexpr (FromSlots) {
                         const uint32_t sl = M.fwd[leaf_role(ra, N0, P)];
@@ -710,6 +732,10 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                     } else {
                         a[k] = ld3(M.leaf + ra);
                     }
+                } else if constexpr (WB) {
+                    const Pack4<T> p = ld4(M.outv + ((uint64_t)L.outoff[j] + ra));
+                    a[k] = Vec3<T>{p.x, p.y, p.z};
+                    la = p.w;
                 } else {
                     a[k] = ld3(M.outv + ((uint64_t)L.outoff[j] + ra));
                 }
@@ -720,8 +746,19 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                     } else {
                         b[k] = ld3(M.leaf + rb);
                     }
+                } else if constexpr (WB) {
+                    const Pack4<T> p = ld4(M.outv + ((uint64_t)L.outoff[h] + rb));
+                    b[k] = Vec3<T>{p.x, p.y, p.z};
+                    lb = p.w;
                 } else {
                     b[k] = ld3(M.outv + ((uint64_t)L.outoff[h] + rb));
+                }
+                if constexpr (WB) {
+                    // Sec. 4.4: def:2 is 1 + min, def:3 is 1 + mean of the inputs' lengths
+#pragma clang fp contract(off)
+                    len[k] = wbk == WB_MIN ? T(1) + (la < lb ? la : lb) : (la + lb) * T(0.5) + T(1);
+                } else {
+                    len[k] = T(0);
                 }
             }
 #pragma unroll
@@ -736,10 +773,10 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                 for (int e = 0; e < 2; ++e) {
                     const uint32_t o = 2u * c + (uint32_t)e;
                     if (o < Rl) {
-                        st3(M.outv + ((uint64_t)oo + o), out[e].x, out[e].y, out[e].z);
+                        st4(M.outv + ((uint64_t)oo + o), out[e].x, out[e].y, out[e].z, len[k]);
                     } else {
                         const uint32_t r = fp + (o - Rl);
-                        st3(M.fin + r, out[e].x, out[e].y, out[e].z);
+                        st4(M.fin + r, out[e].x, out[e].y, out[e].z, len[k]);
                         const double d = (double)out[e].x - mx;
                         sfin += d * d;
                     }
@@ -861,6 +898,7 @@ __device__ __forceinline__ void write_stats(CellStats* st, uint32_t n, const Cel
     s.attempts = sh.attempts;
     s.R0 = sh.R0;
     s.n_th = sh.n_th;
+    s.wb_th = sh.wb_th;
     s.borrowed = sh.borrowed;
     s.folds = sh.folds;
     s.status = 0;

@@ -67,7 +67,7 @@ __device__ unsigned long long g_maxcell[12];
 
 constexpr int kUnroll = 2;
 
-template <typename T, int NT, int G>
+template <typename T, int NT, int G, bool WB = false>
 __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, uint32_t n_work, uint32_t blk,
                                               uint32_t lv_stride)
 {
@@ -263,7 +263,8 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
 
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
-        bottom_up<T, G, false>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
+        bottom_up<T, G, false, WB>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin,
+                                   WB ? uni(I->wb) : 0u);
         TRMC_PHASE(4);
 
         double all[7] = {sums[0], sums[1], sums[2], sums[3], sums[4], sums[5], sfin};
@@ -271,6 +272,12 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
         const uint32_t td = gsum_u32<G>(dummies, gl.redu);
         const uint32_t tv = gsum_u32<G>(viol, gl.redu);
         if (tid == 0) {
+            if constexpr (WB) {
+                sh.rs[0] = all[2];
+                sh.rs[1] = all[3];
+                sh.rs[2] = all[4];
+                sh.rs[3] = all[5];
+            }
             sh.kept0 = all[0];
             sh.dummies = td;
             sh.viol = tv;
@@ -294,10 +301,65 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     }
 
     // ---- 4. Maxwellian remainder and write-back ------------------------------
-    const uint32_t N0 = sh.N0, R0 = sh.R0, n_th = sh.n_th, P = n - N0;
+    const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
     const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
+    [[maybe_unused]] const T wb_max = WB ? (T)uni(I->wb_mmax) : T(0);
+    if constexpr (WB) {
+        // tree-shape truncation (Sec. 4.4): finals longer than m_max join the
+        // remainder; their dropped values join the removed set of the rescale.
+        // Normals of every thermalized slot and the dropped finals' sums.
+        double zs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (uint32_t s = tid; s < n; s += G) {
+            const uint32_t i = M.role[s];
+            bool th = i >= leaf_end;
+            if (i >= kept_end && i < leaf_end) {
+                const Pack4<T> f = ld4(M.fin + leaf_rank(i, N0, P));
+                if (f.w > wb_max) {
+                    th = true;
+                    const double dx = (double)f.x - mx, dy = (double)f.y - my, dz = (double)f.z - mz;
+                    zs[4] += dx;
+                    zs[5] += dy;
+                    zs[6] += dz;
+                    zs[7] += dx * dx + dy * dy + dz * dz;
+                    zs[8] += 1.0;
+                }
+            }
+            if (th) {
+                const Vec3<T> z = Draws<T>::normals(key, s);  // keyed by the slot
+                const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
+                zs[0] += zx;
+                zs[1] += zy;
+                zs[2] += zz;
+                zs[3] += zx * zx + zy * zy + zz * zz;
+            }
+        }
+        gsum<G, 9>(zs, gl.red);
+        if (tid == 0) {
+            const uint32_t n_wb = (uint32_t)zs[8];
+            const uint32_t total = sh.n_th + n_wb;
+            sh.wb_th = n_wb;
+            sh.n_th = total;
+            if (total >= 2) {
+                const double nt = (double)total;
+                const double d0 = (sh.rs[0] + zs[4]) / nt, d1 = (sh.rs[1] + zs[5]) / nt, d2 = (sh.rs[2] + zs[6]) / nt;
+                sh.ur[0] = mx + d0;
+                sh.ur[1] = my + d1;
+                sh.ur[2] = mz + d2;
+                double E = (sh.rs[3] + zs[7]) - nt * (d0 * d0 + d1 * d1 + d2 * d2);
+                E = E > 0.0 ? E : 0.0;
+                const double zb0 = zs[0] / nt, zb1 = zs[1] / nt, zb2 = zs[2] / nt;
+                const double Z = zs[3] - nt * (zb0 * zb0 + zb1 * zb1 + zb2 * zb2);
+                sh.zbar[0] = zb0;
+                sh.zbar[1] = zb1;
+                sh.zbar[2] = zb2;
+                sh.a_th = Z > 0.0 ? sqrt(E / Z) : 0.0;
+            }
+        }
+        gsync<G>();
+    }
+    const uint32_t n_th = sh.n_th;
     const bool thermalize = n_th >= 2;
-    if (thermalize) {
+    if (!WB && thermalize) {
         // sums of the normals of the thermalized slots (keyed by the slot); the
         // write-back draws the same normals again and rescales them (cheaper
         // than storing and reloading them)
@@ -356,10 +418,15 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
                 const uint32_t i = ro[u];
                 const bool lf = s0 + u * G < n && i >= kept_end && i < leaf_end;
                 const uint32_t r = lf ? leaf_rank(i, N0, P) : 0u;
-                const Vec3<T> f = ld3(M.fin + (lf ? r : 0u));
+                const Pack4<T> f = ld4(M.fin + (lf ? r : 0u));
                 fx[u] = f.x;
                 fy[u] = f.y;
                 fz[u] = f.z;
+                if constexpr (WB) {
+                    // a final longer than m_max is replaced (when the remainder
+                    // is a single particle it keeps the final's value)
+                    if (lf && thermalize && f.w > wb_max) ro[u] = leaf_end;
+                }
             }
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {
@@ -412,6 +479,16 @@ k_collide<float>(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_bi
 {
     collide_entry<float>(big, n_big, lv_big, small, n_small, lv_small);
 }
+
+// Cells of instances with tree-shape truncation: one workgroup per cell.
+template <typename T>
+__global__ __launch_bounds__(kCollideThreads) void k_collide_wb(const CellRef* __restrict__ work, uint32_t n_work,
+                                                                uint32_t lv_stride)
+{
+    collide_cells<T, kCollideThreads, kCollideThreads, true>(work, n_work, blockIdx.x, lv_stride);
+}
+template __global__ void k_collide_wb<float>(const CellRef*, uint32_t, uint32_t);
+template __global__ void k_collide_wb<double>(const CellRef*, uint32_t, uint32_t);
 
 template <>
 __global__ __launch_bounds__(kCollideThreads) void k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,

@@ -17,6 +17,8 @@ namespace trmc {
 template <typename T>
 __global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
 template <typename T>
+__global__ void k_collide_wb(const CellRef*, uint32_t, uint32_t);
+template <typename T>
 __global__ void k_hist(const CellRef*, const uint32_t*, uint32_t);
 __global__ void k_scan_tiles(const CellRef*, const uint32_t*, uint32_t);
 __global__ void k_scan_cells(const CellRef*);
@@ -123,6 +125,8 @@ int validate(const trmc_desc* d)
     if (d->m_cap < 1 || d->m_cap > kMaxDepth) return TRMC_EINVAL;
     if (d->m_init < 1 || d->m_init > d->m_cap) return TRMC_EINVAL;
     if (d->trunc == TRMC_ADAPTIVE && !(d->delta1 > 0.0 && d->delta1 < d->delta2)) return TRMC_EINVAL;
+    if (d->wb > TRMC_WB_MEAN) return TRMC_EINVAL;
+    if (d->wb != TRMC_WB_OFF && (d->trunc == TRMC_ADAPTIVE || d->wb_mmax < 1)) return TRMC_EINVAL;
     if (d->m_state0) {
         for (uint32_t c = 0; c < nc; ++c)
             if (d->m_state0[c] < 1 || d->m_state0[c] > d->m_cap) return TRMC_EINVAL;
@@ -150,10 +154,11 @@ struct trmc_ctx {
     uint32_t max_inst = 0, max_cells = 0;
     uint32_t* error = nullptr;
     // work lists of the collision step, [precision: 0 FP32, 1 FP64][class]: class 0 =
-    // workgroup per cell, 1 = wave per cell, 2 = tiled pipeline (large homogeneous cells)
-    CellRef* work[2][3] = {};
-    uint32_t n_work[2][3] = {};
-    uint32_t lv_stride[2][3] = {{2, 2, 2}, {2, 2, 2}};
+    // workgroup per cell, 1 = wave per cell, 2 = tiled pipeline (large homogeneous
+    // cells), 3 = workgroup per cell with tree-shape truncation
+    CellRef* work[2][4] = {};
+    uint32_t n_work[2][4] = {};
+    uint32_t lv_stride[2][4] = {{2, 2, 2, 2}, {2, 2, 2, 2}};
     uint32_t* tile_prefix[2] = {nullptr, nullptr};  // [n_work[k][2] + 1] first tile of each tiled cell
     uint32_t n_tiles[2] = {0, 0};
     uint32_t* cls_list[2] = {nullptr, nullptr};   // [2 * max_cells] light / heavy cells of the step
@@ -181,7 +186,7 @@ namespace {
 
 size_t ctx_bytes(uint32_t max_inst, uint32_t max_cells)
 {
-    return al(sizeof(uint32_t)) + 6 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
+    return al(sizeof(uint32_t)) + 8 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
            2 * al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1)) +
            2 * (al(sizeof(uint32_t) * 2 * std::max(1u, max_cells)) + al(2 * sizeof(uint32_t))) +
            2 * (al(sizeof(CellRef) * max_inst) + 2 * al(sizeof(uint32_t) * (max_inst + 1))) +
@@ -193,13 +198,14 @@ int hip_status(hipError_t e) { return e == hipSuccess ? 0 : TRMC_EIO; }
 // Rebuild the device work lists and the instance list.  The path of a cell comes
 // from the schedule bucket of its expected size; WAVE and TILED need m_cap <=
 // kSmallDepth (which bounds the level arrays of eight cells in LDS) and TILED a
-// homogeneous cell, else the cell takes GROUP.  Lists are ordered by expected
-// size, largest first.
+// homogeneous cell, else the cell takes GROUP.  Cells of instances with
+// tree-shape truncation take their own workgroup-per-cell list.  Lists are
+// ordered by expected size, largest first.
 int rebuild_tables(trmc_ctx* c)
 {
-    std::vector<std::pair<double, CellRef>> order[2][3];
+    std::vector<std::pair<double, CellRef>> order[2][4];
     std::vector<InstDev*> ptrs;
-    uint32_t stride[2][3] = {{2, 2, 2}, {2, 2, 2}};
+    uint32_t stride[2][4] = {{2, 2, 2, 2}, {2, 2, 2, 2}};
     for (auto& s : c->slots) {
         if (!s.active) continue;
         ptrs.push_back(s.dev);
@@ -216,13 +222,14 @@ int rebuild_tables(trmc_ctx* c)
         int cls = 0;
         if (path == TRMC_PATH_TILED && !slab && shallow) cls = 2;
         else if (path == TRMC_PATH_WAVE && shallow) cls = 1;
+        if (s.desc.wb != TRMC_WB_OFF) cls = 3;
         for (uint32_t cc = 0; cc < nc; ++cc) order[k][cls].push_back({per, CellRef{s.dev, cc, 0}});
         stride[k][cls] = std::max(stride[k][cls], s.desc.m_cap + 2u);
     }
     std::vector<CellRef> w;
     std::vector<uint32_t> prefix;
     for (int k = 0; k < 2; ++k) {
-        for (int cls = 0; cls < 3; ++cls) {
+        for (int cls = 0; cls < 4; ++cls) {
             auto& o = order[k][cls];
             std::stable_sort(o.begin(), o.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
             w.clear();
@@ -346,6 +353,8 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     h.step = d->step0;
     h.cur = 0;
     h.n_tiles = L.n_tiles;
+    h.wb = d->wb;
+    h.wb_mmax = d->wb_mmax;
     h.length = d->length;
     h.dt = d->dt;
     const double volume = d->geometry == TRMC_SLAB1D ? d->length / (double)nc : d->length;
@@ -456,6 +465,10 @@ int launch_collide(trmc_ctx* c, int k)
         hipLaunchKernelGGL(k_collide<T>, dim3(nb + small_blocks), dim3(kCollideThreads), lds, c->stream,
                            c->work[k][0], nb, c->lv_stride[k][0], c->work[k][1], ns, c->lv_stride[k][1]);
     }
+    if (const uint32_t nw = c->n_work[k][3]) {
+        hipLaunchKernelGGL(k_collide_wb<T>, dim3(nw), dim3(kCollideThreads), sizeof(uint32_t) * 5 * c->lv_stride[k][3],
+                           c->stream, c->work[k][3], nw, c->lv_stride[k][3]);
+    }
     return hip_status(hipGetLastError());
 }
 
@@ -526,7 +539,7 @@ int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trm
     c->error = reinterpret_cast<uint32_t*>(c->ws + p);
     p += al(sizeof(uint32_t));
     for (int k = 0; k < 2; ++k) {
-        for (int cls = 0; cls < 3; ++cls) {
+        for (int cls = 0; cls < 4; ++cls) {
             c->work[k][cls] = reinterpret_cast<CellRef*>(c->ws + p);
             p += al(sizeof(CellRef) * std::max(1u, max_cells));
         }
@@ -764,6 +777,7 @@ int trmc_moments(trmc_ctx* c, uint32_t slot, trmc_cell_moments* host_out, uint32
         o.violations = st[i].violations;
         o.work_collisions = st[i].work_collisions;
         o.thermalized = st[i].n_th;
+        o.wb_thermalized = st[i].wb_th;
         o.borrowed = st[i].borrowed;
         o.m_eff = st[i].m_eff;
         o.m_used = st[i].m_used;

@@ -9,6 +9,7 @@ namespace trmc {
 enum : uint32_t { GEOM_HOMOG = 1, GEOM_SLAB = 2 };
 enum : uint32_t { PREC_FP64 = 1, PREC_FP32 = 2 };
 enum : uint32_t { TRUNC_NATURAL = 0, TRUNC_FIXED = 1, TRUNC_ADAPTIVE = 2 };
+enum : uint32_t { WB_OFF = 0, WB_MIN = 1, WB_MEAN = 2 };  // tree-shape truncation (Sec. 4.4)
 enum : uint32_t { CELL_OVERFLOW = 1u };
 
 constexpr uint32_t kMaxDepth = 2048;     // largest m_cap accepted
@@ -27,7 +28,7 @@ constexpr uint32_t kSmallDepth = 256;  // ... if their m_cap is at most this
 
 // Counters of one cell's last collision step.
 struct CellStats {
-    uint32_t n, N0, m_eff, m_used, attempts, R0, n_th, borrowed, folds, status;
+    uint32_t n, N0, m_eff, m_used, attempts, R0, n_th, borrowed, folds, status, wb_th, pad;
     unsigned long long collisions, dummies, violations, work_collisions;
     double q, g, E1;
 };
@@ -45,6 +46,7 @@ struct InstDev {
     uint32_t m_init, m_cap, seed, uid;
     uint32_t step, cur;     // next step index; slab: buffer holding the state
     uint32_t n_tiles, pad0;
+    uint32_t wb, wb_mmax;   // tree-shape truncation: WB_* and m_max
     double length, dt, rho_factor, alpha, delta1, delta2, inv_dx;
     const double* eps_cells;  // [n_cells]
     uint32_t* cell_off;       // [n_cells + 1]

@@ -71,10 +71,20 @@ def _ws(T, **kw):
     dict(n_particles=100, eps=0.0), dict(n_particles=100, alpha=1.5), dict(n_particles=100, trunc=9),
     dict(n_particles=100, m_cap=0), dict(n_particles=100, m_cap=5000), dict(n_particles=100, m_init=70),
     dict(n_particles=100, trunc=2, delta1=0.02, delta2=0.01), dict(n_particles=100, particle_weight=-1.0),
+    # tree-shape truncation: unknown definition, m_max 0, combined with the adaptive depth
+    dict(n_particles=100, trunc=1, wb=3), dict(n_particles=100, trunc=1, wb=1, wb_mmax=0),
+    dict(n_particles=100, trunc=2, wb=2, wb_mmax=5),
 ])
 def test_invalid_descriptors_rejected(T, bad):
     rc, _ = _ws(T, **bad)
     assert rc == -22
+
+
+@pytest.mark.parametrize("ok", [dict(n_particles=100, trunc=1, wb=1, wb_mmax=1),
+                                dict(n_particles=100, trunc=0, wb=2, wb_mmax=64)])
+def test_tree_shape_truncation_descriptors_accepted(T, ok):
+    rc, n = _ws(T, **ok)
+    assert rc == 0 and n > 0
 
 
 def test_workspace_size_grows_with_particles(T):

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 INT_FIELDS = [("N0", "N0"), ("m_eff", "m_eff"), ("R0", "R0"), ("thermalized", "n_th"), ("borrowed", "borrowed"),
               ("collisions", "collisions"), ("dummies", "dummies"), ("attempts", "attempts"),
-              ("m_used", "m_used"), ("m_state", "m_state_after")]
+              ("m_used", "m_used"), ("m_state", "m_state_after"), ("wb_thermalized", "wb_th")]
 
 
 @pytest.fixture(scope="module")
@@ -48,7 +48,7 @@ def run_gpu(T, insts, arrays, steps):
 def oracle_of(orc, gi, a):
     kw = dict(seed=gi.seed, uid=gi.uid, dt=gi.dt, eps=gi.eps, alpha=gi.alpha, trunc=gi.trunc, m_init=gi.m_init,
               m_cap=gi.m_cap, delta1=gi.delta1, delta2=gi.delta2, length=gi.length, weight=gi.particle_weight,
-              step=gi.step0)
+              step=gi.step0, wb=gi.wb, wb_mmax=gi.wb_mmax)
     if gi.geometry == 2:
         kw.update(geometry=orc.SLAB, n_cells=gi.n_cells, eps_cells=gi.eps_cells, x=a["x"])
     return orc.Instance(a["vx"], a["vy"], a["vz"], **kw)
