@@ -158,6 +158,47 @@ def batching_speedup(T, N, eps, alpha, init, seed, prec, table, stride=16, steps
             "batched_ms_per_step": batched * 1e3, "speedup": alone / batched}
 
 
+def tree_shape_truncation(T, n_inst, seed, steps=5):
+    """Tree-shape truncation (Sec. 4.4) beside the plain step on one workload:
+    n_inst homogeneous hard-sphere instances of 50,000 bi-Maxwellian particles
+    (the paper's homogeneous test size), eps = 0.2, fixed depth 24, FP32 with
+    FP64 sums.  Plain, def:2 with m_max 2 and def:3 with m_max 3, same keys."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    n = 50_000
+    out = {"workload": f"{n_inst} homogeneous hard-sphere instances x {n} particles, bi-Maxwellian, eps 0.2, "
+                       "dt 0.05, fixed depth 24, fp32", "particles": n_inst * n}
+    for name, wb, mmax in (("plain", T.WB_OFF, 1), ("def2_mmax2", T.WB_MIN, 2), ("def3_mmax3", T.WB_MEAN, 3)):
+        insts, parts = [], []
+        for i in range(n_inst):
+            a = W.bimaxwellian(n, seed, 5000 + i)
+            insts.append(T.Instance(n_particles=n, eps=0.2, alpha=1.0, dt=0.05, trunc=T.FIXED, m_init=24, m_cap=64,
+                                    precision=T.FP32_MIXED, uid=5000 + i, seed=seed, wb=wb, wb_mmax=mmax))
+            parts.append({k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in zip(("vx", "vy", "vz"), a)})
+        ctx = T.Context(insts, parts)
+        ctx.use_graph(True)
+        ctx.step(1)
+        ctx.sync()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        ctx.sync()
+        dt = (time.perf_counter() - t0) / steps
+        mom = [ctx.moments(k) for k in range(n_inst)]
+        th = sum(int(m["thermalized"][0]) for m in mom)
+        wbt = sum(int(m["wb_thermalized"][0]) for m in mom)
+        coll = sum(int(m["collisions"][0]) for m in mom)
+        out[name] = {"ms_per_step": dt * 1e3, "particle_steps_per_s": n_inst * n / dt,
+                     "thermalized_fraction": th / (n_inst * n), "tree_shape_fraction": wbt / (n_inst * n),
+                     "collisions_per_particle": coll / (n_inst * n)}
+        ctx.close()
+        del ctx, parts
+        torch.cuda.empty_cache()
+        log(f"tree-shape truncation {name}: {out[name]}")
+    return out
+
+
 def serving(T, args):
     """Serving run: a Poisson stream of homogeneous solves and shock tubes (N
     log-uniform in [1e3, 1e6], 50-500 steps, eps log-uniform in [1e-4, 1]) served
@@ -206,6 +247,8 @@ def main():
     ap.add_argument("--speedup-stride", type=int, default=16,
                     help="compare batched and one-at-a-time stepping on every n-th instance (0 = skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="HBM budget of the running requests")
+    ap.add_argument("--wb-instances", type=int, default=64,
+                    help="instances of the tree-shape truncation comparison (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB each (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -310,6 +353,8 @@ def main():
         log("batched versus one instance at a time ...")
         line["batching"] = batching_speedup(T, N, eps, alpha, init, args.seed, prec, table, args.speedup_stride)
         log(f"batching: {line['batching']}")
+    if args.wb_instances > 0:
+        line["tree_shape_truncation"] = tree_shape_truncation(T, args.wb_instances, args.seed)
     if args.serve_seconds > 0:
         line["serving"] = serving(T, args)
     if not args.no_cpu_baseline:
