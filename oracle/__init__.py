@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "trmc_oracle.c")
 _LIB = os.path.join(_HERE, "libtrmc_oracle.so")
 
 HOMOG, SLAB = 1, 2
-NATURAL, FIXED, ADAPTIVE = 0, 1, 2
+NATURAL, FIXED, ADAPTIVE, ADAPTIVE_REUSE = 0, 1, 2, 3
 WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
 
 

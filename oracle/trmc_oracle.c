@@ -61,7 +61,17 @@
  *       joins the removed set whose momentum and energy the rescale keeps, so
  *       the step stays conservative.  Twin outputs share a length, so they are
  *       thermalized together.  Not combined with the adaptive depth (the
- *       paper leaves that combination open).
+ *       paper leaves that combination open);
+ *   R16 adaptive depth with reuse (ORC_ADAPTIVE_REUSE, the efficient form of
+ *       Sec. 4.3): a rejected attempt at depth m is kept, with its collisions,
+ *       leaves and finals; the attempt at 2m splits with the same draws, takes
+ *       the levels 1..m as done (no own samples), and builds the trees of the
+ *       levels m+1..2m in level order on top: their requests to levels <= m are
+ *       served by new collisions whose draw indices continue after the earlier
+ *       ones, their leaves are the next roles of the pool, and their finals
+ *       continue the leaf ranks.  An odd request count at a done level leaves
+ *       one more final of that level.  Leaves running out fold only the new
+ *       levels.  Counters add up over the attempts; nothing is discarded.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) with
  * key {seed, uid} and counter {index, tag<<24 | aux, cell, step}.
@@ -287,7 +297,7 @@ static uint32_t tree_choice(const stream_key* s, uint32_t l, uint64_t c)
  *   - each collision chooses j uniformly in {0..l-1} and asks level j and level
  *     l-1-j for one input each, in that order.
  * Returns R_0, the number of leaves (initial-density samples) needed. */
-static void tree_build(tree_t* t, const stream_key* s)
+static void tree_build(tree_t* t, const stream_key* s, const uint64_t* coff)
 {
     uint32_t me = t->me;
     for (uint32_t l = 0; l <= me; ++l) { t->R[l] = 0; t->C[l] = 0; t->F[l] = 0; t->first[l] = 0; }
@@ -301,7 +311,8 @@ static void tree_build(tree_t* t, const stream_key* s)
         t->C[l] = Cl;
         t->first[l] = t->ncoll;
         for (uint64_t c = 0; c < Cl; ++c) {
-            uint32_t j = tree_choice(s, l, c);
+            /* coff: collisions of level l in earlier attempts (reuse, reading R16) */
+            uint32_t j = tree_choice(s, l, (coff ? coff[l] : 0) + c);
             uint64_t ra = t->R[j]++;
             uint64_t rb = t->R[l - 1 - j]++;
             tree_push(t, j, ra, rb);
@@ -452,8 +463,10 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
     rec->g = g;
 
     uint32_t m;
+    const int reuse = cp->trunc == ORC_ADAPTIVE_REUSE;
+    const int adaptive = cp->trunc == ORC_ADAPTIVE || reuse;
     if (cp->trunc == ORC_FIXED) m = cp->m_init;
-    else if (cp->trunc == ORC_ADAPTIVE) m = *m_state;
+    else if (adaptive) m = *m_state;
     else m = cp->m_cap;
     if (m < 1) m = 1;
     if (m > cp->m_cap) m = cp->m_cap;
@@ -484,6 +497,13 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
 
     uint64_t work_coll = 0;
     uint64_t nth_acc = 0; /* thermalized slots of the accepted attempt */
+    /* Reuse of rejected attempts (reading R16): levels 1..mprev are done, their
+     * collisions kept; cprev[l] counts level l's collisions so far (draw offset);
+     * leaf and final ranks continue from R0prev. */
+    uint64_t* cprev = calloc(cap_levels, sizeof *cprev);
+    if (!cprev) abort();
+    uint64_t R0prev = 0, coll_acc = 0;
+    uint32_t mprev = 0, folds_acc = 0;
     uint32_t attempts = 0;
     roles_t ro;
     uint64_t dummies = 0, viol = 0;
@@ -506,12 +526,15 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         uint64_t split_rem = rem;
         T.me = k;
         T.N[k + 1] = rem;
+        /* Reuse: the samples of levels 1..mprev were made by earlier attempts. */
+        if (reuse)
+            for (uint32_t l = 1; l <= mprev && l <= T.me; ++l) T.N[l] = 0;
 
         /* Collision trees (Alg. 4.3, reading R5); fold if the leaves run out. */
         uint32_t folds = 0;
         for (;;) {
-            tree_build(&T, key);
-            if (T.R0 <= n) break;
+            tree_build(&T, key, reuse ? cprev : NULL);
+            if (R0prev + T.R0 <= n || T.me <= mprev) break;
             T.N[T.me] += T.N[T.me + 1];
             T.me -= 1;
             folds++;
@@ -520,9 +543,9 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         ro.n = n;
         ro.N0 = (uint32_t)N0;
         ro.P = (uint64_t)n - N0;
-        ro.R0 = T.R0;
-        ro.borrowed = T.R0 > ro.P ? T.R0 - ro.P : 0;
-        ro.n_th = T.R0 < ro.P ? ro.P - T.R0 : 0;
+        ro.R0 = R0prev + T.R0;
+        ro.borrowed = ro.R0 > ro.P ? ro.R0 - ro.P : 0;
+        ro.n_th = ro.R0 < ro.P ? ro.P - ro.R0 : 0;
         memcpy(ro.pk, pk, sizeof pk);
 
         /* Tree-shape truncation (reading R15): finals whose tree is longer than
@@ -536,22 +559,25 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         }
 
         /* Leaves: initial-density samples, i.e. the particles' current velocities. */
-        for (uint64_t r = 0; r < T.R0; ++r) leaf[r] = v[leaf_slot(&ro, r)];
+        for (uint64_t r = R0prev; r < ro.R0; ++r) leaf[r] = v[leaf_slot(&ro, r)];
 
         /* Collisions, shallowest level first; outputs of level l are out[l][0..2C_l). */
-        dummies = 0;
-        viol = 0;
+        if (!reuse) {
+            dummies = 0;
+            viol = 0;
+        }
         uint64_t nf = 0;
         for (uint32_t l = 1; l <= T.me; ++l) {
             out[l] = xrealloc(out[l], sizeof(vec3) * (size_t)(2 * T.C[l] + 1));
             for (uint64_t c = 0; c < T.C[l]; ++c) {
                 uint64_t id = T.first[l] + c;
                 uint32_t j = T.jch[id], h = l - 1 - j;
-                vec3 a = (j == 0) ? leaf[T.rA[id]] : out[j][T.rA[id]];
-                vec3 b = (h == 0) ? leaf[T.rB[id]] : out[h][T.rB[id]];
+                vec3 a = (j == 0) ? leaf[R0prev + T.rA[id]] : out[j][T.rA[id]];
+                vec3 b = (h == 0) ? leaf[R0prev + T.rB[id]] : out[h][T.rB[id]];
                 uint32_t b0[4], b1[4];
-                draw(key, (uint32_t)c, TAG_COLL, l | (0u << 20), b0);
-                draw(key, (uint32_t)c, TAG_COLL, l | (1u << 20), b1);
+                uint32_t cg = (uint32_t)((reuse ? cprev[l] : 0) + c);
+                draw(key, cg, TAG_COLL, l | (0u << 20), b0);
+                draw(key, cg, TAG_COLL, l | (1u << 20), b1);
                 double xi1 = unif53(b0[0], b1[0]);
                 double xi2 = unif53(b0[1], b1[1]);
                 double xacc = unif53(b0[2], b1[2]);
@@ -559,7 +585,7 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
                     dummies++;
             }
             /* Finals of level l: the outputs no deeper request took. */
-            for (uint64_t o = T.R[l]; o < 2 * T.C[l]; ++o) fin[nf++] = out[l][o];
+            for (uint64_t o = T.R[l]; o < 2 * T.C[l]; ++o) fin[R0prev + nf++] = out[l][o];
         }
         /* nf == R0 by construction: every output is either taken or final. */
         if (nf != T.R0) abort();
@@ -620,17 +646,17 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         rec->N0 = (uint32_t)N0;
         rec->m_eff = T.me;
         rec->m_used = m;
-        rec->R0 = (uint32_t)T.R0;
+        rec->R0 = (uint32_t)ro.R0;
         nth_acc = nth;
         rec->n_th = (uint32_t)nth;
         rec->wb_th = (uint32_t)n_wb;
         rec->borrowed = (uint32_t)ro.borrowed;
-        rec->folds = folds;
-        rec->collisions = T.ncoll;
+        rec->folds = folds_acc + folds;
+        rec->collisions = coll_acc + T.ncoll;
         rec->dummies = dummies;
         rec->violations = viol;
 
-        if (cp->trunc != ORC_ADAPTIVE) break;
+        if (!adaptive) break;
 
         /* Adaptive depth (Sec. 4.3, reading R8). */
         double Snew = 0.0;
@@ -639,7 +665,7 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
             double d = v[kept_slot(&ro, i)].x - mean.x;
             Snew += d * d;
         }
-        for (uint64_t r = 0; r < T.R0; ++r) {
+        for (uint64_t r = 0; r < ro.R0; ++r) {
             double d = fin[r].x - mean.x;
             Snew += d * d;
         }
@@ -659,8 +685,16 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         if (E1 < cp->delta1) { *m_state = m / 2 > 1 ? m / 2 : 1; break; }
         if (E1 <= cp->delta2) { *m_state = m; break; }
         if (m >= cp->m_cap || split_rem == 0) { *m_state = m; break; }
+        if (reuse) {
+            for (uint32_t l = 1; l <= T.me; ++l) cprev[l] += T.C[l];
+            R0prev = ro.R0;
+            mprev = m;
+            coll_acc += T.ncoll;
+            folds_acc += folds;
+        }
         m = 2 * m < cp->m_cap ? 2 * m : cp->m_cap;
     }
+    free(cprev);
 
     /* Write the accepted result: leaf slots take the finals, thermalized slots
      * take the rescaled Maxwellian samples, the rest are unchanged. */
@@ -711,7 +745,8 @@ int orc_run(const orc_desc* d, uint64_t n, double* x, double* vx, double* vy, do
     uint32_t nc = d->geometry == ORC_SLAB ? d->n_cells : 1u;
     if (nc == 0) return -1;
     if (d->geometry == ORC_SLAB && !x) return -1;
-    if (d->wb > ORC_WB_MEAN || (d->wb != ORC_WB_OFF && (d->trunc == ORC_ADAPTIVE || d->wb_mmax < 1))) return -1;
+    if (d->trunc > ORC_ADAPTIVE_REUSE) return -1;
+    if (d->wb > ORC_WB_MEAN || (d->wb != ORC_WB_OFF && (d->trunc >= ORC_ADAPTIVE || d->wb_mmax < 1))) return -1;
     double volume = d->geometry == ORC_SLAB ? d->length / (double)nc : d->length;
     double rho_factor = d->weight / volume;
 
@@ -847,7 +882,7 @@ int64_t orc_tree(uint32_t seed, uint32_t uid, uint32_t cell, uint32_t step, uint
     orc_split(seed, uid, cell, step, n, q, m, T.N, &me);
     T.me = me;
     for (;;) {
-        tree_build(&T, &key);
+        tree_build(&T, &key, NULL);
         if (T.R0 <= n) break;
         T.N[T.me] += T.N[T.me + 1];
         T.me -= 1;

@@ -7,7 +7,7 @@
 #include <stdint.h>
 
 enum { ORC_HOMOG = 1, ORC_SLAB = 2 };
-enum { ORC_NATURAL = 0, ORC_FIXED = 1, ORC_ADAPTIVE = 2 };
+enum { ORC_NATURAL = 0, ORC_FIXED = 1, ORC_ADAPTIVE = 2, ORC_ADAPTIVE_REUSE = 3 };
 enum { ORC_WB_OFF = 0, ORC_WB_MIN = 1, ORC_WB_MEAN = 2 }; /* tree-shape truncation, Sec. 4.4 */
 
 typedef struct {
