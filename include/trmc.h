@@ -51,7 +51,10 @@ extern "C" {
 /* truncation of the collision trees */
 #define TRMC_NATURAL 0  /* depth limited only by m_cap */
 #define TRMC_FIXED 1    /* depth m_init every step */
-#define TRMC_ADAPTIVE 2 /* depth adapted per cell from m_init (Sec. 4.3) */
+#define TRMC_ADAPTIVE 2 /* depth adapted per cell from m_init (Sec. 4.3); a rejected attempt is
+                           recomputed at twice the depth */
+#define TRMC_ADAPTIVE_REUSE 3 /* as TRMC_ADAPTIVE, but a rejected attempt is kept and the levels
+                                 m+1..2m are built on top of it (Sec. 4.3, collisions reused) */
 /* tree-shape truncation (Sec. 4.4, TRMC-WB of Alg. 4.6): a final sample whose
    collision tree is longer than wb_mmax is replaced by a Maxwellian sample */
 #define TRMC_WB_OFF 0  /* off */
@@ -75,13 +78,13 @@ typedef struct trmc_desc {
     double eps;             /* Knudsen number, used when eps_cells is NULL */
     const double* eps_cells;/* host [n_cells] Knudsen number per cell, or NULL */
     double alpha;           /* VHS exponent of B = K |q|^alpha, K = 1/(4 pi): 0 Maxwell molecules, 1 hard spheres */
-    uint32_t trunc;         /* TRMC_NATURAL / TRMC_FIXED / TRMC_ADAPTIVE */
+    uint32_t trunc;         /* TRMC_NATURAL / TRMC_FIXED / TRMC_ADAPTIVE / TRMC_ADAPTIVE_REUSE */
     uint32_t m_init;        /* initial (ADAPTIVE) or fixed (FIXED) depth, >= 1 */
     uint32_t m_cap;         /* maximum depth, 1 .. 2048 */
     uint32_t step0;         /* index of the first step (restart from a saved state) */
     double delta1, delta2;  /* adaptive thresholds, 0 < delta1 < delta2 (Sec. 4.3) */
     const uint32_t* m_state0; /* host [n_cells] saved adaptive depths, or NULL (use m_init) */
-    uint32_t wb;            /* TRMC_WB_OFF / TRMC_WB_MIN / TRMC_WB_MEAN; not with TRMC_ADAPTIVE */
+    uint32_t wb;            /* TRMC_WB_OFF / TRMC_WB_MIN / TRMC_WB_MEAN; not with the adaptive depth */
     uint32_t wb_mmax;       /* m_max of the tree-shape truncation, >= 1 */
 } trmc_desc;
 

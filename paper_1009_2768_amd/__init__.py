@@ -16,10 +16,11 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _abi
-from ._abi import (ADAPTIVE, FIXED, FP32_MIXED, FP64, HOMOG, NATURAL, PATH_DEFAULT, PATH_GROUP, PATH_TILED,
+from ._abi import (ADAPTIVE, ADAPTIVE_REUSE, FIXED, FP32_MIXED, FP64, HOMOG, NATURAL, PATH_DEFAULT, PATH_GROUP, PATH_TILED,
                    PATH_WAVE, SCHED_BUCKETS, SLAB1D, WB_MEAN, WB_MIN, WB_OFF, TrmcError, check)
 
 __all__ = ["Instance", "Context", "HOMOG", "SLAB1D", "FP64", "FP32_MIXED", "NATURAL", "FIXED", "ADAPTIVE",
+           "ADAPTIVE_REUSE",
            "PATH_DEFAULT", "PATH_GROUP", "PATH_WAVE", "PATH_TILED", "SCHED_BUCKETS", "WB_OFF", "WB_MIN",
            "WB_MEAN", "TrmcError", "load", "size_bucket"]
 

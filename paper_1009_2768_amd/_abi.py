@@ -8,7 +8,7 @@ from . import build as _build
 
 HOMOG, SLAB1D = 1, 2
 FP64, FP32_MIXED = 1, 2
-NATURAL, FIXED, ADAPTIVE = 0, 1, 2
+NATURAL, FIXED, ADAPTIVE, ADAPTIVE_REUSE = 0, 1, 2, 3
 WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
 
 EINVAL, ENOMEM, ENOSPC, EIO, EOVERFLOW = -22, -12, -28, -5, -75

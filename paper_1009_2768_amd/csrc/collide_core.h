@@ -390,7 +390,7 @@ __device__ __forceinline__ void cell_params(const InstDev* I, uint32_t cell, uin
     sh.q = q;
     uint32_t m;
     if (I->trunc == TRUNC_FIXED) m = I->m_init;
-    else if (I->trunc == TRUNC_ADAPTIVE) m = I->m_state[cell];
+    else if (I->trunc == TRUNC_ADAPTIVE || I->trunc == TRUNC_ADAPTIVE_REUSE) m = I->m_state[cell];
     else m = I->m_cap;
     if (m < 1) m = 1;
     if (m > I->m_cap) m = I->m_cap;
@@ -447,11 +447,16 @@ __device__ __forceinline__ void split_levels(const Key& key, uint32_t n, double 
 //    R_0 exceed n, the deepest level is folded into the remainder.  Returns the
 //    number of collisions (uniform over the group); sets sh.R0, sh.me, sh.folds
 //    and sh.overflow (capacity).
-template <int G>
+//    REUSE (adaptive depth keeping a rejected attempt, Sec. 4.3): the trees are
+//    built on top of earlier attempts' -- collision c of level l draws with index
+//    coff[l] + c, the leaves fit when r0prev + R0 <= n, and only levels above
+//    mfloor are folded.
+template <int G, bool REUSE = false>
 __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32_t n, uint64_t cap,
                                                           const Levels& L, GroupLds<G>& gl, CellShared& sh,
                                                           gptr<uint32_t> jarr, gptr<uint32_t> rA, gptr<uint32_t> rB,
-                                                          uint32_t tid)
+                                                          uint32_t tid, const uint32_t* coff = nullptr,
+                                                          uint32_t r0prev = 0, uint32_t mfloor = 0)
 {
     constexpr int NWG = G / 64;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
@@ -478,10 +483,15 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
                 break;
             }
             const uint32_t fst = (uint32_t)ncoll;
+            [[maybe_unused]] const uint32_t c_off = REUSE ? uni(coff[l]) : 0u;
             if (l <= 64u) {
                 for (uint32_t b0 = 0; b0 < Cl; b0 += G) {
                     // sub-level choices: one Philox block per 4 collisions
-                    if (tid < G / 4u && b0 + 4u * tid < Cl) {
+                    if constexpr (REUSE) {
+                        // the index offset need not be a multiple of 4: every lane
+                        // draws its own collision's block
+                        if (b0 + tid < Cl) gl.jbuf[tid] = (uint16_t)tree_choice(key, l, c_off + b0 + tid);
+                    } else if (tid < G / 4u && b0 + 4u * tid < Cl) {
                         const uint4 wv = draw(key, (b0 >> 2) + tid, TAG_TREE, l);
                         gl.jbuf[4 * tid + 0] = (uint16_t)__umulhi(wv.x, l);
                         gl.jbuf[4 * tid + 1] = (uint16_t)__umulhi(wv.y, l);
@@ -540,7 +550,7 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
                     for (uint32_t b0 = 0; b0 < Cl; b0 += 64u) {
                         const uint32_t c = b0 + lane;
                         const bool valid = c < Cl;
-                        const uint32_t j = valid ? tree_choice(key, l, c) : 0u;
+                        const uint32_t j = valid ? tree_choice(key, l, (REUSE ? c_off : 0u) + c) : 0u;
                         const uint32_t ta = j, tb = l - 1u - j;
                         bool pa = valid, pb = valid;
                         uint32_t rkA = 0, rkB = 0;
@@ -585,7 +595,7 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
         }
         if (tid == 0) sh.R0 = L.run[0];
         gsync_lds<G>();
-        if (sh.R0 <= n) break;
+        if (REUSE ? (r0prev + sh.R0 <= n || me <= mfloor) : sh.R0 <= n) break;
         if (tid == 0) {
             L.N[me] += L.N[me + 1];
             sh.me = me - 1u;
@@ -697,22 +707,26 @@ __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, 
 #endif
 constexpr int kBU = TRMC_BOTTOM_UP_BATCH;  // collisions per thread per batch in bottom_up
 
-template <typename T, int G, bool FromSlots, bool WB = false>
+template <typename T, int G, bool FromSlots, bool WB = false, bool REUSE = false>
 __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const T> vx, gptr<const T> vy,
                                           gptr<const T> vz,
                                           const Levels& L, const CellShared& sh, const CellMem<T>& M,
                                           unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
-                                          uint32_t& dummies, uint32_t& viol, double& sfin, uint32_t wbk = 0)
+                                          uint32_t& dummies, uint32_t& viol, double& sfin, uint32_t wbk = 0,
+                                          const uint32_t* coff = nullptr, uint32_t r0prev = 0)
 {
     const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
     unsigned long long above = ncoll;  // collisions of deeper levels precede level l's
-    uint32_t fp = 0;                   // finals of shallower levels
+    uint32_t fp = REUSE ? r0prev : 0u; // finals of shallower levels (and of earlier attempts)
+    // leaves of this attempt: ranks from r0prev on (reuse) or from 0
+    const gptr<Pack4<T>> leafb = M.leaf + (REUSE ? r0prev : 0u);
     for (uint32_t l = 1; l <= me; ++l) {
         const uint32_t Cl = uni(L.C[l]), Rl = uni(L.Rtot[l]);
         if (Cl == 0) continue;
         above -= Cl;
         const uint32_t fst = (uint32_t)above;
         const uint32_t oo = uni(L.outoff[l]);
+        [[maybe_unused]] const uint32_t c_off = REUSE ? uni(coff[l]) : 0u;
         // kBU collisions per thread: every index and input load of the batch
         // is issued before the first collision is computed
         for (uint32_t c0 = tid; c0 < Cl; c0 += G * kBU) {
@@ -730,7 +744,7 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                         const uint32_t sl = M.fwd[leaf_role(ra, N0, P)];
                         a[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
                     } else {
-                        a[k] = ld3(M.leaf + ra);
+                        a[k] = ld3(leafb + ra);
                     }
                 } else if constexpr (WB) {
                     const Pack4<T> p = ld4(M.outv + ((uint64_t)L.outoff[j] + ra));
@@ -744,7 +758,7 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                         const uint32_t sl = M.fwd[leaf_role(rb, N0, P)];
                         b[k] = Vec3<T>{vx[sl], vy[sl], vz[sl]};
                     } else {
-                        b[k] = ld3(M.leaf + rb);
+                        b[k] = ld3(leafb + rb);
                     }
                 } else if constexpr (WB) {
                     const Pack4<T> p = ld4(M.outv + ((uint64_t)L.outoff[h] + rb));
@@ -766,7 +780,7 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                 const uint32_t c = c0 + (uint32_t)k * G;
                 if (c >= Cl) break;
                 T xi1, xi2, xacc;
-                Draws<T>::coll(key, l, c, xi1, xi2, xacc);
+                Draws<T>::coll(key, l, REUSE ? c_off + c : c, xi1, xi2, xacc);
                 Vec3<T> out[2];
                 if (!collide<T>(a[k], b[k], xi1, xi2, xacc, alpha, gT, out[0], out[1], viol)) dummies++;
 #pragma unroll
@@ -812,7 +826,7 @@ __device__ __forceinline__ void decide(InstDev* I, uint32_t cell, uint32_t n, co
     }
     uint32_t decision = 1;  // accept
     sh.E1 = 0.0;
-    if (I->trunc == TRUNC_ADAPTIVE) {
+    if (I->trunc == TRUNC_ADAPTIVE || I->trunc == TRUNC_ADAPTIVE_REUSE) {
         const uint32_t m = sh.m;
         if (sh.Sn == 0.0) {
             I->m_state[cell] = m;

@@ -67,7 +67,7 @@ __device__ unsigned long long g_maxcell[12];
 
 constexpr int kUnroll = 2;
 
-template <typename T, int NT, int G, bool WB = false>
+template <typename T, int NT, int G, bool WB = false, bool REUSE = false>
 __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, uint32_t n_work, uint32_t blk,
                                               uint32_t lv_stride)
 {
@@ -227,12 +227,36 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     uint32_t leaves_done = 0;  // leaf ranks [0, leaves_done) are gathered
     uint32_t attempt = 0;
     bool pooled = false;
+    // Reuse of rejected attempts (adaptive depth, Sec. 4.3): levels 1..mprev are
+    // done, coff[l] counts level l's collisions so far (the draw offset of the
+    // next ones), leaf and final ranks continue from r0prev.
+    [[maybe_unused]] uint32_t* const coff =
+        REUSE ? lds_levels + (size_t)NGRP * 5u * lv_stride + (size_t)grp * lv_stride : nullptr;
+    [[maybe_unused]] uint32_t r0prev = 0, mprev = 0, folds_acc = 0, dum_acc = 0, viol_acc = 0;
+    [[maybe_unused]] unsigned long long coll_acc = 0;
+    [[maybe_unused]] double sfin_acc = 0.0;
+    if constexpr (REUSE) {
+        for (uint32_t l = tid; l < lv_stride; l += G) coff[l] = 0;  // visible after the split's barrier
+    }
     for (;;) {
+        [[maybe_unused]] const uint32_t m_att = REUSE ? uni(sh.m) : 0u;
         split_levels<G>(key, n, sh.q, L, sh, tid);
+        if constexpr (REUSE) {
+            if (mprev) {
+                const uint32_t me0 = uni(sh.me);
+                for (uint32_t l = 1 + tid; l <= mprev && l <= me0; l += G) L.N[l] = 0;  // made earlier
+                gsync_lds<G>();
+            }
+        }
         TRMC_PHASE(1);
-        const unsigned long long ncoll = build_trees<G>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
+        const unsigned long long ncoll =
+            build_trees<G, REUSE>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid, coff, r0prev, mprev);
         TRMC_PHASE(2);
         if (sh.overflow) break;
+        if constexpr (REUSE) {
+            if (tid == 0) sh.R0 += r0prev;  // leaves of all attempts
+            gsync_lds<G>();
+        }
         if (!level_offsets<G>(n, ncoll, M.ocap, L, sh, tid)) break;
 
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
@@ -263,9 +287,13 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
 
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
-        bottom_up<T, G, false, WB>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin,
-                                   WB ? uni(I->wb) : 0u);
+        bottom_up<T, G, false, WB, REUSE>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol,
+                                          sfin, WB ? uni(I->wb) : 0u, coff, r0prev);
         TRMC_PHASE(4);
+        if constexpr (REUSE) {
+            sfin_acc += sfin;  // the finals of every attempt enter S
+            sfin = sfin_acc;
+        }
 
         double all[7] = {sums[0], sums[1], sums[2], sums[3], sums[4], sums[5], sfin};
         gsum<G, 7>(all, gl.red);
@@ -281,11 +309,29 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
             sh.kept0 = all[0];
             sh.dummies = td;
             sh.viol = tv;
+            if constexpr (REUSE) {
+                sh.dummies += dum_acc;
+                sh.viol += viol_acc;
+                sh.ncoll += coll_acc;
+                sh.folds += folds_acc;
+            }
             decide(I, cell, n, all, mx, my, mz, sh);
         }
         gsync<G>();
         TRMC_PHASE(5);
         if (sh.decision) break;
+        if constexpr (REUSE) {
+            // keep this attempt: the next one builds on top of it
+            const uint32_t me_a = uni(sh.me);
+            for (uint32_t l = 1 + tid; l <= me_a; l += G) coff[l] += L.C[l];
+            r0prev = uni(sh.R0);
+            mprev = m_att;
+            coll_acc = uni((uint64_t)sh.ncoll);
+            folds_acc = uni(sh.folds);
+            dum_acc = uni(sh.dummies);
+            viol_acc = uni(sh.viol);
+            gsync_lds<G>();
+        }
     }
 
     if (sh.overflow) {
@@ -489,6 +535,17 @@ __global__ __launch_bounds__(kCollideThreads) void k_collide_wb(const CellRef* _
 }
 template __global__ void k_collide_wb<float>(const CellRef*, uint32_t, uint32_t);
 template __global__ void k_collide_wb<double>(const CellRef*, uint32_t, uint32_t);
+
+// Cells of instances with the adaptive depth that keeps rejected attempts: one
+// workgroup per cell (dynamic LDS: level arrays, then the draw offsets).
+template <typename T>
+__global__ __launch_bounds__(kCollideThreads) void k_collide_reuse(const CellRef* __restrict__ work,
+                                                                   uint32_t n_work, uint32_t lv_stride)
+{
+    collide_cells<T, kCollideThreads, kCollideThreads, false, true>(work, n_work, blockIdx.x, lv_stride);
+}
+template __global__ void k_collide_reuse<float>(const CellRef*, uint32_t, uint32_t);
+template __global__ void k_collide_reuse<double>(const CellRef*, uint32_t, uint32_t);
 
 template <>
 __global__ __launch_bounds__(kCollideThreads) void k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,

@@ -8,7 +8,7 @@ namespace trmc {
 
 enum : uint32_t { GEOM_HOMOG = 1, GEOM_SLAB = 2 };
 enum : uint32_t { PREC_FP64 = 1, PREC_FP32 = 2 };
-enum : uint32_t { TRUNC_NATURAL = 0, TRUNC_FIXED = 1, TRUNC_ADAPTIVE = 2 };
+enum : uint32_t { TRUNC_NATURAL = 0, TRUNC_FIXED = 1, TRUNC_ADAPTIVE = 2, TRUNC_ADAPTIVE_REUSE = 3 };
 enum : uint32_t { WB_OFF = 0, WB_MIN = 1, WB_MEAN = 2 };  // tree-shape truncation (Sec. 4.4)
 enum : uint32_t { CELL_OVERFLOW = 1u };
 

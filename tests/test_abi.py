@@ -73,7 +73,8 @@ def _ws(T, **kw):
     dict(n_particles=100, trunc=2, delta1=0.02, delta2=0.01), dict(n_particles=100, particle_weight=-1.0),
     # tree-shape truncation: unknown definition, m_max 0, combined with the adaptive depth
     dict(n_particles=100, trunc=1, wb=3), dict(n_particles=100, trunc=1, wb=1, wb_mmax=0),
-    dict(n_particles=100, trunc=2, wb=2, wb_mmax=5),
+    dict(n_particles=100, trunc=2, wb=2, wb_mmax=5), dict(n_particles=100, trunc=3, wb=1, wb_mmax=5),
+    dict(n_particles=100, trunc=4), dict(n_particles=100, trunc=3, delta1=0.02, delta2=0.01),
 ])
 def test_invalid_descriptors_rejected(T, bad):
     rc, _ = _ws(T, **bad)
