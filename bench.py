@@ -39,7 +39,7 @@ def make_batch(n_inst: int, seed: int, scale: float = 1.0):
     return N, eps, alpha, init
 
 
-def build_context(T, N, eps, alpha, init, seed, precision, device="cuda", uids=None):
+def build_context(T, N, eps, alpha, init, seed, precision, device="cuda", uids=None, trunc=None):
     import numpy as np
     import torch
 
@@ -60,7 +60,8 @@ def build_context(T, N, eps, alpha, init, seed, precision, device="cuda", uids=N
         vy[sl].copy_(torch.from_numpy(a[1]))
         vz[sl].copy_(torch.from_numpy(a[2]))
         insts.append(T.Instance(n_particles=n, eps=float(eps[i]), alpha=float(alpha[i]), dt=0.05,
-                                trunc=T.ADAPTIVE, m_init=2, m_cap=64, precision=precision, uid=uid, seed=seed))
+                                trunc=T.ADAPTIVE if trunc is None else trunc, m_init=2, m_cap=64,
+                                precision=precision, uid=uid, seed=seed))
         parts.append({"vx": vx[sl], "vy": vy[sl], "vz": vz[sl], "x": None})
     ctx = T.Context(insts, parts)
     return ctx, (vx, vy, vz)
@@ -158,6 +159,49 @@ def batching_speedup(T, N, eps, alpha, init, seed, prec, table, stride=16, steps
             "batched_ms_per_step": batched * 1e3, "speedup": alone / batched}
 
 
+def work_totals(T, ctx):
+    """Collisions of the accepted results and over all adaptive attempts, and the
+    cells that redid their step, in the last step of every instance."""
+    coll = work = redo = 0
+    for k in range(len(ctx.instances)):
+        m = ctx.moments(k)
+        coll += int(m["collisions"].sum())
+        work += int(m["work_collisions"].sum())
+        redo += int((m["attempts"] > 1).sum())
+    return {"collisions": coll, "work_collisions": work, "cells_redone": redo}
+
+
+def adaptive_reuse(T, N, eps, alpha, init, seed, prec, table, steps, warmup):
+    """The benchmark workload with the adaptive depth that keeps rejected attempts
+    (Sec. 4.3, the collisions of the wrong depth reused) instead of recomputing
+    them: same instances, schedule and timing."""
+    import numpy as np
+    import torch
+    ctx, bufs = build_context(T, N, eps, alpha, init, seed, prec, trunc=T.ADAPTIVE_REUSE)
+    ctx.set_schedule(table)
+    ctx.use_graph(True)
+    for _ in range(warmup):
+        ctx.step(1)
+    ctx.sync()
+    stream = ctx.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for s in range(steps):
+            ev[s][0].record(stream)
+            ctx.step(1)
+            ev[s][1].record(stream)
+    ctx.sync()
+    wall = time.perf_counter() - t0
+    out = {"ms_per_step": wall * 1e3 / steps, "kernel_ms": float(np.mean([a.elapsed_time(b) for a, b in ev])),
+           "particle_steps_per_s": int(N.sum()) * steps / wall}
+    out.update(work_totals(T, ctx))
+    ctx.close()
+    del ctx, bufs
+    torch.cuda.empty_cache()
+    return out
+
+
 def tree_shape_truncation(T, n_inst, seed, steps=5):
     """Tree-shape truncation (Sec. 4.4) beside the plain step on one workload:
     n_inst homogeneous hard-sphere instances of 50,000 bi-Maxwellian particles
@@ -247,6 +291,8 @@ def main():
     ap.add_argument("--speedup-stride", type=int, default=16,
                     help="compare batched and one-at-a-time stepping on every n-th instance (0 = skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="HBM budget of the running requests")
+    ap.add_argument("--no-reuse", action="store_true",
+                    help="skip the run of the workload with the adaptive depth that keeps rejected attempts")
     ap.add_argument("--wb-instances", type=int, default=64,
                     help="instances of the tree-shape truncation comparison (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -346,9 +392,16 @@ def main():
                      "kernel": (kernel + " (+ k_advance, about 4 us)") if not tiled else
                      "tile pipeline + " + kernel + " (several kernels per step)"},
     }
+    recompute_work = work_totals(T, ctx)
     ctx.close()
     del ctx, bufs
     torch.cuda.empty_cache()
+    if not args.no_reuse:
+        log("adaptive depth keeping rejected attempts ...")
+        reuse = adaptive_reuse(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup)
+        line["adaptive_reuse"] = {"recompute": dict(ms_per_step=ms_per_step, kernel_ms=avg_ms, **recompute_work),
+                                  "reuse": reuse, "speedup": ms_per_step / reuse["ms_per_step"]}
+        log(f"adaptive reuse: {line['adaptive_reuse']}")
     if args.speedup_stride > 0:
         log("batched versus one instance at a time ...")
         line["batching"] = batching_speedup(T, N, eps, alpha, init, args.seed, prec, table, args.speedup_stride)

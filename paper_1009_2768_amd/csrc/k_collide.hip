@@ -499,14 +499,14 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
 
 // Cells of the workgroup-per-cell list occupy the first n_big workgroups, cells
 // of the wave-per-cell list (eight per workgroup) the rest.
-template <typename T>
+template <typename T, bool REUSE = false>
 __device__ __forceinline__ void collide_entry(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big,
                                               const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small)
 {
     if (blockIdx.x < n_big)
-        collide_cells<T, kCollideThreads, kCollideThreads>(big, n_big, blockIdx.x, lv_big);
+        collide_cells<T, kCollideThreads, kCollideThreads, false, REUSE>(big, n_big, blockIdx.x, lv_big);
     else
-        collide_cells<T, kCollideThreads, 64>(small, n_small, blockIdx.x - n_big, lv_small);
+        collide_cells<T, kCollideThreads, 64, false, REUSE>(small, n_small, blockIdx.x - n_big, lv_small);
 }
 
 // The per-cell chains are latency bound, so resident waves matter: the FP32
@@ -536,16 +536,28 @@ __global__ __launch_bounds__(kCollideThreads) void k_collide_wb(const CellRef* _
 template __global__ void k_collide_wb<float>(const CellRef*, uint32_t, uint32_t);
 template __global__ void k_collide_wb<double>(const CellRef*, uint32_t, uint32_t);
 
-// Cells of instances with the adaptive depth that keeps rejected attempts: one
-// workgroup per cell (dynamic LDS: level arrays, then the draw offsets).
+// Cells of instances with the adaptive depth that keeps rejected attempts, on
+// the same two paths as k_collide (dynamic LDS per group: level arrays, then
+// the draw offsets of each group).
 template <typename T>
-__global__ __launch_bounds__(kCollideThreads) void k_collide_reuse(const CellRef* __restrict__ work,
-                                                                   uint32_t n_work, uint32_t lv_stride)
+__global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
+
+template <>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(TRMC_F32_WAVES_PER_EU, 8))) void
+k_collide_reuse<float>(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big,
+                       const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small)
 {
-    collide_cells<T, kCollideThreads, kCollideThreads, false, true>(work, n_work, blockIdx.x, lv_stride);
+    collide_entry<float, true>(big, n_big, lv_big, small, n_small, lv_small);
 }
-template __global__ void k_collide_reuse<float>(const CellRef*, uint32_t, uint32_t);
-template __global__ void k_collide_reuse<double>(const CellRef*, uint32_t, uint32_t);
+
+template <>
+__global__ __launch_bounds__(kCollideThreads) void k_collide_reuse<double>(const CellRef* __restrict__ big,
+                                                                           uint32_t n_big, uint32_t lv_big,
+                                                                           const CellRef* __restrict__ small,
+                                                                           uint32_t n_small, uint32_t lv_small)
+{
+    collide_entry<double, true>(big, n_big, lv_big, small, n_small, lv_small);
+}
 
 template <>
 __global__ __launch_bounds__(kCollideThreads) void k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,

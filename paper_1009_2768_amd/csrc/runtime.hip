@@ -19,7 +19,7 @@ __global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, ui
 template <typename T>
 __global__ void k_collide_wb(const CellRef*, uint32_t, uint32_t);
 template <typename T>
-__global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t);
+__global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
 template <typename T>
 __global__ void k_hist(const CellRef*, const uint32_t*, uint32_t);
 __global__ void k_scan_tiles(const CellRef*, const uint32_t*, uint32_t);
@@ -157,11 +157,11 @@ struct trmc_ctx {
     uint32_t* error = nullptr;
     // work lists of the collision step, [precision: 0 FP32, 1 FP64][class]: class 0 =
     // workgroup per cell, 1 = wave per cell, 2 = tiled pipeline (large homogeneous
-    // cells), 3 = workgroup per cell with tree-shape truncation, 4 = workgroup per
-    // cell with the adaptive depth that keeps rejected attempts
-    CellRef* work[2][5] = {};
-    uint32_t n_work[2][5] = {};
-    uint32_t lv_stride[2][5] = {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}};
+    // cells), 3 = workgroup per cell with tree-shape truncation; 4 and 5 = as 0
+    // and 1 for the adaptive depth that keeps rejected attempts
+    CellRef* work[2][6] = {};
+    uint32_t n_work[2][6] = {};
+    uint32_t lv_stride[2][6] = {{2, 2, 2, 2, 2, 2}, {2, 2, 2, 2, 2, 2}};
     uint32_t* tile_prefix[2] = {nullptr, nullptr};  // [n_work[k][2] + 1] first tile of each tiled cell
     uint32_t n_tiles[2] = {0, 0};
     uint32_t* cls_list[2] = {nullptr, nullptr};   // [2 * max_cells] light / heavy cells of the step
@@ -189,7 +189,7 @@ namespace {
 
 size_t ctx_bytes(uint32_t max_inst, uint32_t max_cells)
 {
-    return al(sizeof(uint32_t)) + 10 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
+    return al(sizeof(uint32_t)) + 12 * al(sizeof(CellRef) * std::max(1u, max_cells)) +
            2 * al(sizeof(uint32_t) * (std::max(1u, max_cells) + 1)) +
            2 * (al(sizeof(uint32_t) * 2 * std::max(1u, max_cells)) + al(2 * sizeof(uint32_t))) +
            2 * (al(sizeof(CellRef) * max_inst) + 2 * al(sizeof(uint32_t) * (max_inst + 1))) +
@@ -207,9 +207,9 @@ int hip_status(hipError_t e) { return e == hipSuccess ? 0 : TRMC_EIO; }
 // expected size, largest first.
 int rebuild_tables(trmc_ctx* c)
 {
-    std::vector<std::pair<double, CellRef>> order[2][5];
+    std::vector<std::pair<double, CellRef>> order[2][6];
     std::vector<InstDev*> ptrs;
-    uint32_t stride[2][5] = {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}};
+    uint32_t stride[2][6] = {{2, 2, 2, 2, 2, 2}, {2, 2, 2, 2, 2, 2}};
     for (auto& s : c->slots) {
         if (!s.active) continue;
         ptrs.push_back(s.dev);
@@ -227,14 +227,14 @@ int rebuild_tables(trmc_ctx* c)
         if (path == TRMC_PATH_TILED && !slab && shallow) cls = 2;
         else if (path == TRMC_PATH_WAVE && shallow) cls = 1;
         if (s.desc.wb != TRMC_WB_OFF) cls = 3;
-        else if (s.desc.trunc == TRMC_ADAPTIVE_REUSE) cls = 4;
+        else if (s.desc.trunc == TRMC_ADAPTIVE_REUSE) cls = cls == 1 ? 5 : 4;
         for (uint32_t cc = 0; cc < nc; ++cc) order[k][cls].push_back({per, CellRef{s.dev, cc, 0}});
         stride[k][cls] = std::max(stride[k][cls], s.desc.m_cap + 2u);
     }
     std::vector<CellRef> w;
     std::vector<uint32_t> prefix;
     for (int k = 0; k < 2; ++k) {
-        for (int cls = 0; cls < 5; ++cls) {
+        for (int cls = 0; cls < 6; ++cls) {
             auto& o = order[k][cls];
             std::stable_sort(o.begin(), o.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
             w.clear();
@@ -474,10 +474,13 @@ int launch_collide(trmc_ctx* c, int k)
         hipLaunchKernelGGL(k_collide_wb<T>, dim3(nw), dim3(kCollideThreads), sizeof(uint32_t) * 5 * c->lv_stride[k][3],
                            c->stream, c->work[k][3], nw, c->lv_stride[k][3]);
     }
-    if (const uint32_t nr = c->n_work[k][4]) {
-        hipLaunchKernelGGL(k_collide_reuse<T>, dim3(nr), dim3(kCollideThreads),
-                           sizeof(uint32_t) * 6 * c->lv_stride[k][4], c->stream, c->work[k][4], nr,
-                           c->lv_stride[k][4]);
+    const uint32_t rb = c->n_work[k][4], rs = c->n_work[k][5];
+    if (rb + rs) {
+        const uint32_t small_blocks = (rs + kSmallPerBlock - 1) / kSmallPerBlock;
+        const size_t lds = std::max(sizeof(uint32_t) * 6 * c->lv_stride[k][4],
+                                    sizeof(uint32_t) * 6 * kSmallPerBlock * c->lv_stride[k][5]);
+        hipLaunchKernelGGL(k_collide_reuse<T>, dim3(rb + small_blocks), dim3(kCollideThreads), lds, c->stream,
+                           c->work[k][4], rb, c->lv_stride[k][4], c->work[k][5], rs, c->lv_stride[k][5]);
     }
     return hip_status(hipGetLastError());
 }
@@ -549,7 +552,7 @@ int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trm
     c->error = reinterpret_cast<uint32_t*>(c->ws + p);
     p += al(sizeof(uint32_t));
     for (int k = 0; k < 2; ++k) {
-        for (int cls = 0; cls < 5; ++cls) {
+        for (int cls = 0; cls < 6; ++cls) {
             c->work[k][cls] = reinterpret_cast<CellRef*>(c->ws + p);
             p += al(sizeof(CellRef) * std::max(1u, max_cells));
         }

@@ -134,3 +134,34 @@ def test_beside_plain_adaptive_equals_alone(trmc):
     for k in ("vx", "vy", "vz"):
         np.testing.assert_array_equal(ga[k], ga1[k])
         np.testing.assert_array_equal(gb[k], gb1[k])
+
+
+def test_wave_path_matches_oracle(trmc, orc):
+    """Small cells on the wave-per-cell path (eight cells per workgroup)."""
+    T = trmc
+    sizes = [256, 300, 511, 700, 1000, 1500, 1999, 450, 820]
+    insts, arrs = [], []
+    for k, n in enumerate(sizes):
+        a = W.bkw(n, 0.6, seed=7, stream=80 + k) if k % 2 else W.bimaxwellian(n, seed=7, stream=80 + k)
+        arrs.append({"vx": a[0], "vy": a[1], "vz": a[2]})
+        kw = FORCE if k % 3 == 0 else {}
+        insts.append(T.Instance(n_particles=n, eps=[0.02, 0.1, 0.5][k % 3], alpha=float(k % 2),
+                                trunc=T.ADAPTIVE_REUSE, m_init=2, m_cap=64, uid=80 + k, seed=7, precision=T.FP64,
+                                **kw))
+    say(f"reuse fp64 wave path: {len(sizes)} cells of {min(sizes)}..{max(sizes)} particles, 3 steps")
+    parts = [T.device_particles(a["vx"], a["vy"], a["vz"], None, T.FP64) for a in arrs]
+    ctx = T.Context(insts, parts)
+    table = [0] * T.SCHED_BUCKETS
+    for b in range(8, 11):
+        table[b] = T.PATH_WAVE
+    ctx.set_schedule(table)
+    ctx.step(3)
+    res = [(ctx.read(k), ctx.moments(k)) for k in range(len(insts))]
+    ctx.close()
+    redone = 0
+    for inst, a, (got, mom) in zip(insts, arrs, res):
+        o = oracle_of(orc, inst, a)
+        o.run(3)
+        compare(o, got, mom, 1)
+        redone += int(mom["attempts"][0] > 1)
+    assert redone > 0
