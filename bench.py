@@ -392,7 +392,7 @@ def main():
                      "kernel": (kernel + " (+ k_advance, about 4 us)") if not tiled else
                      "tile pipeline + " + kernel + " (several kernels per step)"},
     }
-    recompute_work = work_totals(T, ctx)
+    recompute_work = work_totals(T, ctx) if not args.no_reuse else None
     ctx.close()
     del ctx, bufs
     torch.cuda.empty_cache()
