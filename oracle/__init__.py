@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "libtrmc_oracle.so")
 HOMOG, SLAB = 1, 2
 NATURAL, FIXED, ADAPTIVE, ADAPTIVE_REUSE = 0, 1, 2, 3
 WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
+BC_SPECULAR, BC_INFLOW = 0, 1
 
 
 def build() -> str:
@@ -46,6 +47,7 @@ class _Desc(ctypes.Structure):
         ("trunc", ctypes.c_uint32), ("m_init", ctypes.c_uint32), ("m_cap", ctypes.c_uint32),
         ("delta1", ctypes.c_double), ("delta2", ctypes.c_double),
         ("wb", ctypes.c_uint32), ("wb_mmax", ctypes.c_uint32),
+        ("bc", ctypes.c_uint32), ("in_left", ctypes.c_double * 3), ("in_right", ctypes.c_double * 3),
     ]
 
 
@@ -82,8 +84,12 @@ def lib():
         L.orc_perm.restype = u32
         L.orc_transport.argtypes = [P(dbl), P(dbl), dbl, dbl, u32]
         L.orc_transport.restype = u32
-        L.orc_run.argtypes = [P(_Desc), u64, P(dbl), P(dbl), P(dbl), P(dbl), P(u32), u32, u32,
+        L.orc_run.argtypes = [P(_Desc), P(u64), u64, P(dbl), P(dbl), P(dbl), P(dbl), P(u32), u32, u32,
                               P(CellRecord), P(u32)]
+        L.orc_flux_inverse.argtypes = [dbl, dbl]
+        L.orc_flux_inverse.restype = dbl
+        L.orc_inflow_mean.argtypes = [dbl, dbl, dbl, dbl, dbl]
+        L.orc_inflow_mean.restype = dbl
         L.orc_run.restype = ctypes.c_int
         L.orc_moments.argtypes = [u64, P(dbl), P(dbl), P(dbl), dbl, P(dbl)]
         L.orc_moments.restype = None
@@ -150,6 +156,17 @@ def collide(a, b, xi1, xi2, xacc=0.0, alpha=0.0, g=1.0):
     return oa, ob, bool(acc)
 
 
+def flux_inverse(a: float, u: float) -> float:
+    """Inward normal speed over sigma of a reservoir particle (reading R17) for the
+    uniform u: the inverse of the flux-weighted half-range distribution."""
+    return lib().orc_flux_inverse(float(a), float(u))
+
+
+def inflow_mean(rho: float, u_in: float, T: float, weight: float, dt: float) -> float:
+    """Expected particles entering through one end in one step."""
+    return lib().orc_inflow_mean(float(rho), float(u_in), float(T), float(weight), float(dt))
+
+
 def wb_len(a: float, b: float, kind: int) -> float:
     """Length of a collision's output from its inputs' lengths (Sec. 4.4)."""
     return lib().orc_wb_len(float(a), float(b), int(kind))
@@ -203,18 +220,27 @@ class Instance:
     delta2: float = 0.01
     wb: int = WB_OFF
     wb_mmax: int = 5
+    bc: int = BC_SPECULAR
+    in_left: tuple | None = None   # reservoir (rho, u, T) at x = 0, u along +x
+    in_right: tuple | None = None  # reservoir (rho, u, T) at x = length
+    capacity: int | None = None    # open slab: room for entering particles
     step: int = 0
     m_state: np.ndarray | None = None
     last: list | None = None
 
     def __post_init__(self):
-        self.vx = np.ascontiguousarray(self.vx, dtype=np.float64).copy()
-        self.vy = np.ascontiguousarray(self.vy, dtype=np.float64).copy()
-        self.vz = np.ascontiguousarray(self.vz, dtype=np.float64).copy()
+        self.n_live = len(self.vx)
+        cap = max(self.capacity or 0, self.n_live)
+
+        def buf(a):
+            b = np.zeros(cap)
+            b[:self.n_live] = np.asarray(a, dtype=np.float64)
+            return b
+        self.vx, self.vy, self.vz = buf(self.vx), buf(self.vy), buf(self.vz)
         if self.x is not None:
-            self.x = np.ascontiguousarray(self.x, dtype=np.float64).copy()
+            self.x = buf(self.x)
         if self.weight is None:
-            self.weight = self.length / len(self.vx)
+            self.weight = self.length / max(1, self.n_live)
         nc = self.n_cells if self.geometry == SLAB else 1
         if self.m_state is None:
             self.m_state = np.full(nc, self.m_init, dtype=np.uint32)
@@ -223,7 +249,7 @@ class Instance:
 
     @property
     def n(self) -> int:
-        return len(self.vx)
+        return self.n_live
 
     def _desc(self) -> _Desc:
         d = _Desc()
@@ -234,6 +260,11 @@ class Instance:
         d.trunc, d.m_init, d.m_cap = self.trunc, self.m_init, self.m_cap
         d.delta1, d.delta2 = self.delta1, self.delta2
         d.wb, d.wb_mmax = self.wb, self.wb_mmax
+        d.bc = self.bc
+        if self.in_left is not None:
+            d.in_left = (ctypes.c_double * 3)(*self.in_left)
+        if self.in_right is not None:
+            d.in_right = (ctypes.c_double * 3)(*self.in_right)
         return d
 
     def run(self, n_steps: int = 1):
@@ -243,12 +274,14 @@ class Instance:
         counts = np.zeros(nc, dtype=np.uint32)
         d = self._desc()
         xp = _p(self.x, ctypes.c_double) if self.x is not None else None
-        rc = lib().orc_run(ctypes.byref(d), self.n, xp, _p(self.vx, ctypes.c_double),
+        n_io = ctypes.c_uint64(self.n_live)
+        rc = lib().orc_run(ctypes.byref(d), ctypes.byref(n_io), len(self.vx), xp, _p(self.vx, ctypes.c_double),
                            _p(self.vy, ctypes.c_double), _p(self.vz, ctypes.c_double),
                            _p(self.m_state, ctypes.c_uint32), self.step, n_steps, rec,
                            _p(counts, ctypes.c_uint32))
         if rc != 0:
             raise RuntimeError(f"oracle run failed ({rc})")
+        self.n_live = int(n_io.value)
         self.step += n_steps
         self.last = [rec[i] for i in range(nc)]
         self.counts = counts

@@ -71,7 +71,17 @@
  *       ones, their leaves are the next roles of the pool, and their finals
  *       continue the leaf ranks.  An odd request count at a done level leaves
  *       one more final of that level.  Leaves running out fold only the new
- *       levels.  Counters add up over the attempts; nothing is discarded.
+ *       levels.  Counters add up over the attempts; nothing is discarded;
+ *   R17 open slab for the stationary shock (Sec. 5.2): each end is a reservoir
+ *       with a Maxwellian state (rho, u, T).  Per step, before transport, each
+ *       end injects floor(lambda + U) particles, lambda the expected number that
+ *       cross inward in dt, (rho / weight) sigma (phi(a) + a Phi(a)) dt with a the
+ *       inward drift over sigma = sqrt(T); the inward normal speed is drawn from
+ *       the flux-weighted half-range law by inverting its distribution function,
+ *       the tangential ones from the Maxwellian, and the particle is placed
+ *       outside by the part of the step it has not yet flown.  Particles beyond
+ *       either end after transport are removed.  The left end enters along +x:
+ *       the sign of the paper's inflow velocity only chooses the side.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) with
  * key {seed, uid} and counter {index, tag<<24 | aux, cell, step}.
@@ -112,7 +122,7 @@ void orc_philox(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { TAG_SPLIT = 1, TAG_PERM = 2, TAG_TREE = 3, TAG_COLL = 4, TAG_MAXW = 5 };
+enum { TAG_SPLIT = 1, TAG_PERM = 2, TAG_TREE = 3, TAG_COLL = 4, TAG_MAXW = 5, TAG_INJ = 6 };
 
 typedef struct {
     uint32_t seed, uid, cell, step;
@@ -737,43 +747,156 @@ uint32_t orc_transport(double* x, double* vx, double dt, double L, uint32_t n_ce
 /* ------------------------------------------------------------------------- */
 /* Driver                                                                     */
 /* ------------------------------------------------------------------------- */
-int orc_run(const orc_desc* d, uint64_t n, double* x, double* vx, double* vy, double* vz,
+/* ------------------------------------------------------------------------- */
+/* Open slab (reading R17): reservoirs at both ends.                          */
+/* ------------------------------------------------------------------------- */
+static double std_phi(double t) { return exp(-0.5 * t * t) * 0.3989422804014327; /* 1/sqrt(2 pi) */ }
+static double std_Phi(double t) { return 0.5 * erfc(-t / sqrt(2.0)); }
+
+/* Distribution of w = v_n / sigma for the particles of a Maxwellian of drift
+ * a sigma (along the inward normal) that cross a wall inward in unit time: the
+ * density is proportional to w phi(w - a) on w > 0.  F is its integral from 0
+ * to w; Z = F(infinity) = phi(a) + a Phi(a). */
+static double flux_cdf(double w, double a)
+{
+    return (std_phi(a) - std_phi(w - a)) + a * (std_Phi(w - a) - std_Phi(-a));
+}
+static double flux_norm(double a) { return std_phi(a) + a * std_Phi(a); }
+
+/* Inverse of F at u Z, by 64 bisection steps on [0, max(a, 0) + 12]. */
+double orc_flux_inverse(double a, double u)
+{
+    double target = u * flux_norm(a);
+    double lo = 0.0, hi = (a > 0.0 ? a : 0.0) + 12.0;
+    for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (flux_cdf(mid, a) < target) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Expected number of simulation particles entering through one end in one
+ * step: (rho / weight) * sigma * Z(a) * dt, a = u_in / sigma. */
+double orc_inflow_mean(double rho, double u_in, double T, double weight, double dt)
+{
+    double sigma = sqrt(T);
+    return rho / weight * sigma * flux_norm(u_in / sigma) * dt;
+}
+
+/* Particles entering in one step, appended after the n live ones: left end
+ * first, then right end.  Each enters at a uniform time of the step, so it is
+ * placed outside the slab by the part of the step it has not yet flown.
+ * Returns -2 if the arrays are full (nothing injected). */
+static int inject(const orc_desc* d, uint32_t step, uint64_t* n, uint64_t cap, double* x, double* vx, double* vy,
+                  double* vz)
+{
+    uint64_t k[2];
+    double sig[2], a[2];
+    for (int side = 0; side < 2; ++side) {
+        const double* st = side == 0 ? d->in_left : d->in_right;
+        stream_key key = {d->seed, d->uid, 0xFFFFFFF0u + (uint32_t)side, step};
+        sig[side] = sqrt(st[2]);
+        double u_in = side == 0 ? st[1] : -st[1]; /* drift along the inward normal */
+        a[side] = u_in / sig[side];
+        double lam = orc_inflow_mean(st[0], u_in, st[2], d->weight, d->dt);
+        uint32_t w[4];
+        draw(&key, 0, TAG_INJ, 2, w);
+        k[side] = (uint64_t)floor(lam + unif53(w[0], w[1]));
+    }
+    if (*n + k[0] + k[1] > cap) return -2;
+    uint64_t at = *n;
+    for (int side = 0; side < 2; ++side) {
+        stream_key key = {d->seed, d->uid, 0xFFFFFFF0u + (uint32_t)side, step};
+        for (uint64_t i = 0; i < k[side]; ++i) {
+            uint32_t b0[4], b1[4];
+            draw(&key, (uint32_t)i, TAG_INJ, 0, b0);
+            draw(&key, (uint32_t)i, TAG_INJ, 1, b1);
+            double u0 = unif53(b0[0], b1[0]), u1 = unif53(b0[1], b1[1]);
+            double u2 = unif53(b0[2], b1[2]), u3 = unif53(b0[3], b1[3]);
+            double vn = sig[side] * orc_flux_inverse(a[side], u0);
+            double v = side == 0 ? vn : -vn;
+            double r = sqrt(-2.0 * log(1.0 - u2));
+            double ph = 6.283185307179586 * u3;
+            x[at] = side == 0 ? -v * d->dt * u1 : d->length - v * d->dt * u1;
+            vx[at] = v;
+            vy[at] = sig[side] * (r * cos(ph));
+            vz[at] = sig[side] * (r * sin(ph));
+            at++;
+        }
+    }
+    *n = at;
+    return 0;
+}
+
+/* Free flight out of an open slab: a particle beyond either end has left. */
+static uint32_t transport_open(double* x, double vx, double dt, double L, uint32_t n_cells)
+{
+    double xn = fma(vx, dt, *x);
+    *x = xn;
+    if (xn < 0.0 || xn > L) return n_cells; /* gone */
+    double cf = floor(xn * ((double)n_cells / L));
+    return cf >= (double)n_cells ? n_cells - 1u : (uint32_t)cf;
+}
+
+int orc_run(const orc_desc* d, uint64_t* n_io, uint64_t cap, double* x, double* vx, double* vy, double* vz,
             uint32_t* m_state, uint32_t step0, uint32_t n_steps, orc_cell_record* rec,
             uint32_t* cell_counts)
 {
-    if (!d || !vx || !vy || !vz || !m_state) return -1;
+    if (!d || !n_io || !vx || !vy || !vz || !m_state) return -1;
+    uint64_t n = *n_io;
     uint32_t nc = d->geometry == ORC_SLAB ? d->n_cells : 1u;
     if (nc == 0) return -1;
     if (d->geometry == ORC_SLAB && !x) return -1;
+    if (d->bc > ORC_BC_INFLOW || (d->bc == ORC_BC_INFLOW && d->geometry != ORC_SLAB)) return -1;
+    if (d->bc == ORC_BC_INFLOW) {
+        for (int side = 0; side < 2; ++side) {
+            const double* st = side == 0 ? d->in_left : d->in_right;
+            if (!(st[0] > 0.0) || !(st[2] > 0.0) || !isfinite(st[1])) return -1;
+        }
+    } else if (cap != n) {
+        return -1;
+    }
+    if (n > cap) return -1;
     if (d->trunc > ORC_ADAPTIVE_REUSE) return -1;
     if (d->wb > ORC_WB_MEAN || (d->wb != ORC_WB_OFF && (d->trunc >= ORC_ADAPTIVE || d->wb_mmax < 1))) return -1;
     double volume = d->geometry == ORC_SLAB ? d->length / (double)nc : d->length;
     double rho_factor = d->weight / volume;
 
-    uint32_t* cell = malloc(sizeof(uint32_t) * (n ? n : 1));
-    uint64_t* count = calloc((size_t)nc + 1, sizeof(uint64_t));
-    double* tmp = malloc(sizeof(double) * (n ? n : 1));
-    vec3* cv = malloc(sizeof(vec3) * (n ? n : 1));
+    uint32_t* cell = malloc(sizeof(uint32_t) * (cap ? cap : 1));
+    uint64_t* count = calloc((size_t)nc + 2, sizeof(uint64_t));
+    double* tmp = malloc(sizeof(double) * (cap ? cap : 1));
+    vec3* cv = malloc(sizeof(vec3) * (cap ? cap : 1));
     if (!cell || !count || !tmp || !cv) abort();
+    const int open = d->bc == ORC_BC_INFLOW;
 
     for (uint32_t s = 0; s < n_steps; ++s) {
         uint32_t step = step0 + s;
         uint64_t* start = count;
         if (d->geometry == ORC_SLAB) {
-            /* Transport, then a stable counting sort by cell. */
-            for (uint64_t i = 0; i < n; ++i) cell[i] = orc_transport(&x[i], &vx[i], d->dt, d->length, nc);
-            memset(count, 0, sizeof(uint64_t) * ((size_t)nc + 1));
+            /* Open ends: the reservoirs' particles enter first (reading R17). */
+            if (open && inject(d, step, &n, cap, x, vx, vy, vz) != 0) {
+                free(cell); free(count); free(tmp); free(cv);
+                return -2;
+            }
+            /* Transport, then a stable counting sort by cell; with open ends the
+             * particles that left go to bucket nc and are dropped. */
+            for (uint64_t i = 0; i < n; ++i)
+                cell[i] = open ? transport_open(&x[i], vx[i], d->dt, d->length, nc)
+                               : orc_transport(&x[i], &vx[i], d->dt, d->length, nc);
+            memset(count, 0, sizeof(uint64_t) * ((size_t)nc + 2));
             for (uint64_t i = 0; i < n; ++i) count[cell[i] + 1]++;
-            for (uint32_t c = 0; c < nc; ++c) count[c + 1] += count[c];
-            uint64_t* pos = malloc(sizeof(uint64_t) * nc);
+            for (uint32_t c = 0; c < nc + (uint32_t)open; ++c) count[c + 1] += count[c];
+            uint64_t* pos = malloc(sizeof(uint64_t) * (nc + 1));
             if (!pos) abort();
             double* arrs[4] = {x, vx, vy, vz};
             for (int a = 0; a < 4; ++a) {
-                memcpy(pos, count, sizeof(uint64_t) * nc);
+                memcpy(pos, count, sizeof(uint64_t) * (nc + 1));
                 for (uint64_t i = 0; i < n; ++i) tmp[pos[cell[i]]++] = arrs[a][i];
                 memcpy(arrs[a], tmp, sizeof(double) * n);
             }
             free(pos);
+            n = count[nc]; /* particles still in the slab */
         } else {
             count[0] = 0;
             count[1] = n;
@@ -797,6 +920,7 @@ int orc_run(const orc_desc* d, uint64_t n, double* x, double* vx, double* vy, do
         }
     }
     free(cell); free(count); free(tmp); free(cv);
+    *n_io = n;
     return 0;
 }
 

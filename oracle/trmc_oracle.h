@@ -9,6 +9,7 @@
 enum { ORC_HOMOG = 1, ORC_SLAB = 2 };
 enum { ORC_NATURAL = 0, ORC_FIXED = 1, ORC_ADAPTIVE = 2, ORC_ADAPTIVE_REUSE = 3 };
 enum { ORC_WB_OFF = 0, ORC_WB_MIN = 1, ORC_WB_MEAN = 2 }; /* tree-shape truncation, Sec. 4.4 */
+enum { ORC_BC_SPECULAR = 0, ORC_BC_INFLOW = 1 };          /* slab ends: walls or reservoirs */
 
 typedef struct {
     uint32_t seed, uid;
@@ -24,6 +25,8 @@ typedef struct {
     double delta1, delta2;
     uint32_t wb;         /* ORC_WB_OFF, or thermalize finals longer than wb_mmax under def:2 / def:3 */
     uint32_t wb_mmax;
+    uint32_t bc;         /* ORC_BC_SPECULAR, or ORC_BC_INFLOW: reservoirs at both ends of a slab */
+    double in_left[3], in_right[3]; /* reservoir states (rho, u, T); u along +x */
 } orc_desc;
 
 typedef struct {
@@ -38,7 +41,9 @@ double orc_exp_neg(double x);
 double orc_grid_up(double g);
 uint32_t orc_perm(uint32_t i, uint32_t n, const uint32_t k[4]);
 uint32_t orc_transport(double* x, double* vx, double dt, double L, uint32_t n_cells);
-int orc_run(const orc_desc* d, uint64_t n, double* x, double* vx, double* vy, double* vz,
+double orc_flux_inverse(double a, double u);
+double orc_inflow_mean(double rho, double u_in, double T, double weight, double dt);
+int orc_run(const orc_desc* d, uint64_t* n_io, uint64_t cap, double* x, double* vx, double* vy, double* vz,
             uint32_t* m_state, uint32_t step0, uint32_t n_steps, orc_cell_record* rec,
             uint32_t* cell_counts);
 void orc_moments(uint64_t n, const double* vx, const double* vy, const double* vz, double rho_factor,

@@ -93,6 +93,50 @@ def sod_dt(length: float, n_cells: int, cfl: float = 0.5, v_ref: float = 3.0) ->
     return cfl * (length / n_cells) / v_ref
 
 
+def shock_states(mach: float = 3.0, gamma: float = 5.0 / 3.0, rho1: float = 1.0, T1: float = 1.0):
+    """Upstream and downstream states (rho, u, T) of a stationary normal shock,
+    upstream entering along +x: the Rankine-Hugoniot jump of a monatomic gas
+    (p = rho T, sound speed sqrt(gamma T))."""
+    u1 = mach * math.sqrt(gamma * T1)
+    m2 = mach * mach
+    r = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)   # rho2 / rho1
+    pr = (2.0 * gamma * m2 - (gamma - 1.0)) / (gamma + 1.0)  # p2 / p1
+    rho2 = rho1 * r
+    T2 = T1 * pr / r
+    return (rho1, u1, T1), (rho2, u1 / r, T2)
+
+
+def shock(n_cells: int, ppc_up: int, mach: float = 3.0, length: float = 1.0, seed: int = 0, stream: int = 0,
+          capacity_factor: float = 1.5):
+    """Slab holding a stationary shock at its centre: the upstream state on the left
+    half (ppc_up particles per cell), the downstream state on the right half (as many
+    particles per cell as its density ratio asks).  Returns x, vx, vy, vz, the
+    particle weight, the two states and a capacity for the arrays (room for the
+    reservoirs' particles)."""
+    up, down = shock_states(mach)
+    g = rng(seed, stream)
+    dx = length / n_cells
+    w = up[0] * dx / ppc_up
+    xs, vs = [], []
+    for c in range(n_cells):
+        rho, u, T = up if c < n_cells // 2 else down
+        m = int(round(rho * dx / w))
+        xs.append(c * dx + g.random(m) * dx)
+        v = g.standard_normal((m, 3)) * math.sqrt(T)
+        v[:, 0] += u
+        vs.append(v)
+    x = np.concatenate(xs)
+    v = np.concatenate(vs)
+    cap = int(capacity_factor * len(x)) + 4096
+    return x, v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy(), w, up, down, cap
+
+
+def shock_dt(length: float, n_cells: int, cfl: float = 0.5, mach: float = 3.0) -> float:
+    """dt = CFL * dx / (u1 + 3 sqrt(T1)) with the upstream state of shock_states."""
+    (rho1, u1, T1), _ = shock_states(mach)
+    return cfl * (length / n_cells) / (u1 + 3.0 * math.sqrt(T1))
+
+
 def transition_eps(n_cells: int, lo: float = 1e-4, hi: float = 1.0):
     """eps(x) log-linear from lo to hi across the cells (cell centres)."""
     c = (np.arange(n_cells) + 0.5) / n_cells
