@@ -60,6 +60,11 @@ extern "C" {
 #define TRMC_WB_OFF 0  /* off */
 #define TRMC_WB_MIN 1  /* length 1 + min of the two subtrees' lengths (definition def:2) */
 #define TRMC_WB_MEAN 2 /* length 1 + mean of the two subtrees' lengths (definition def:3) */
+/* ends of a slab */
+#define TRMC_BC_SPECULAR 0 /* specular walls (closed slab) */
+#define TRMC_BC_INFLOW 1   /* open slab (Sec. 5.2 stationary shock): each end is a Maxwellian
+                              reservoir whose particles enter every step; particles that fly
+                              past an end leave.  The particle count changes from step to step. */
 
 typedef struct trmc_ctx trmc_ctx;
 
@@ -86,6 +91,11 @@ typedef struct trmc_desc {
     const uint32_t* m_state0; /* host [n_cells] saved adaptive depths, or NULL (use m_init) */
     uint32_t wb;            /* TRMC_WB_OFF / TRMC_WB_MIN / TRMC_WB_MEAN; not with the adaptive depth */
     uint32_t wb_mmax;       /* m_max of the tree-shape truncation, >= 1 */
+    uint32_t bc;            /* TRMC_BC_SPECULAR or TRMC_BC_INFLOW (TRMC_SLAB1D only) */
+    uint32_t n_live0;       /* TRMC_BC_INFLOW: particles present at admission (<= n_particles,
+                               which is then the capacity of the arrays); otherwise 0 or n_particles */
+    double in_left[3];      /* TRMC_BC_INFLOW: reservoir at x = 0: mass density, mean x velocity, temperature */
+    double in_right[3];     /* TRMC_BC_INFLOW: reservoir at x = length (same units; entries move along -x) */
 } trmc_desc;
 
 /* Caller-owned device arrays of one instance, SoA, n_particles elements each, of
@@ -159,9 +169,17 @@ int trmc_state(trmc_ctx* ctx, uint32_t slot, trmc_particles* out);
 
 /* Copy the current particles of `slot` to host arrays (any may be NULL), in cell
  * order for a slab; m_state (host [n_cells], may be NULL) receives the adaptive
- * depths; *step receives the index of the next step.  Synchronises the stream. */
+ * depths; *step receives the index of the next step.  An open slab copies its
+ * current count (trmc_count) of particles; the arrays must hold n_particles.
+ * Synchronises the stream. */
 int trmc_read(trmc_ctx* ctx, uint32_t slot, void* x, void* vx, void* vy, void* vz, uint32_t* m_state,
               uint32_t* step);
+
+/* Number of particles of `slot` now (an open slab's count changes every step;
+ * otherwise n_particles).  Synchronises the stream.  TRMC_ENOSPC when an open
+ * slab's arrays could not take a step's entering particles (that step injected
+ * none). */
+int trmc_count(trmc_ctx* ctx, uint32_t slot, uint64_t* n_live);
 
 /* Serving: add one instance while others run.  workspace: its own caller-owned
  * device memory of trmc_workspace_size(desc, 1) bytes.  On success *slot receives

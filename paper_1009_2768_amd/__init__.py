@@ -17,12 +17,13 @@ import numpy as np
 
 from . import _abi
 from ._abi import (ADAPTIVE, ADAPTIVE_REUSE, FIXED, FP32_MIXED, FP64, HOMOG, NATURAL, PATH_DEFAULT, PATH_GROUP, PATH_TILED,
-                   PATH_WAVE, SCHED_BUCKETS, SLAB1D, WB_MEAN, WB_MIN, WB_OFF, TrmcError, check)
+                   PATH_WAVE, SCHED_BUCKETS, SLAB1D, WB_MEAN, WB_MIN, WB_OFF, BC_INFLOW, BC_SPECULAR, TrmcError,
+                   check)
 
 __all__ = ["Instance", "Context", "HOMOG", "SLAB1D", "FP64", "FP32_MIXED", "NATURAL", "FIXED", "ADAPTIVE",
            "ADAPTIVE_REUSE",
            "PATH_DEFAULT", "PATH_GROUP", "PATH_WAVE", "PATH_TILED", "SCHED_BUCKETS", "WB_OFF", "WB_MIN",
-           "WB_MEAN", "TrmcError", "load", "size_bucket"]
+           "WB_MEAN", "BC_SPECULAR", "BC_INFLOW", "TrmcError", "load", "size_bucket"]
 
 load = _abi.load
 
@@ -51,6 +52,10 @@ class Instance:
     m_state0: np.ndarray | None = None
     wb: int = WB_OFF  # tree-shape truncation (Sec. 4.4): WB_MIN (def:2) or WB_MEAN (def:3)
     wb_mmax: int = 5
+    bc: int = BC_SPECULAR  # BC_INFLOW: open slab with reservoirs (n_particles is then the capacity)
+    n_live0: int = 0       # open slab: particles present at admission
+    in_left: tuple | None = None   # reservoir (rho, u, T) at x = 0
+    in_right: tuple | None = None  # reservoir (rho, u, T) at x = length
     _keep: list = field(default_factory=list, repr=False)
 
     def to_c(self) -> _abi.Desc:
@@ -67,6 +72,11 @@ class Instance:
         d.trunc, d.m_init, d.m_cap, d.step0 = self.trunc, self.m_init, self.m_cap, self.step0
         d.delta1, d.delta2 = self.delta1, self.delta2
         d.wb, d.wb_mmax = self.wb, self.wb_mmax
+        d.bc, d.n_live0 = self.bc, self.n_live0
+        if self.in_left is not None:
+            d.in_left = (ctypes.c_double * 3)(*self.in_left)
+        if self.in_right is not None:
+            d.in_right = (ctypes.c_double * 3)(*self.in_right)
         self._keep = []
         if self.eps_cells is not None:
             e = np.ascontiguousarray(self.eps_cells, dtype=np.float64)
@@ -234,7 +244,17 @@ class Context:
         check(self._lib.trmc_read(self._ctx, slot, ptr(x), ptr(vx), ptr(vy), ptr(vz),
                                   ms.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(step)),
               "trmc_read")
+        live = self.count(slot)
+        if live != n:
+            x = x[:live] if x is not None else None
+            vx, vy, vz = vx[:live], vy[:live], vz[:live]
         return {"x": x, "vx": vx, "vy": vy, "vz": vz, "m_state": ms, "step": step.value}
+
+    def count(self, slot: int) -> int:
+        """Particles of instance `slot` now (an open slab's count changes every step)."""
+        n = ctypes.c_uint64(0)
+        check(self._lib.trmc_count(self._ctx, slot, ctypes.byref(n)), "trmc_count")
+        return int(n.value)
 
     def state_pointers(self, slot: int):
         p = _abi.Particles()
@@ -242,11 +262,18 @@ class Context:
         return p
 
 
-def device_particles(vx, vy, vz, x=None, precision=FP64, device="cuda"):
-    """Copy host arrays to device tensors of the instance precision."""
+def device_particles(vx, vy, vz, x=None, precision=FP64, device="cuda", capacity=None):
+    """Copy host arrays to device tensors of the instance precision (zero-padded to
+    `capacity` elements for an open slab)."""
     import torch
     dt = torch.float64 if precision == FP64 else torch.float32
-    t = {k: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
-         for k, a in (("vx", vx), ("vy", vy), ("vz", vz))}
-    t["x"] = torch.as_tensor(np.ascontiguousarray(x), dtype=dt).to(device) if x is not None else None
+    n = len(vx)
+    cap = max(n, capacity or 0)
+
+    def dev(a):
+        b = np.zeros(cap)
+        b[:n] = np.asarray(a, dtype=np.float64)
+        return torch.as_tensor(b, dtype=dt).to(device)
+    t = {k: dev(a) for k, a in (("vx", vx), ("vy", vy), ("vz", vz))}
+    t["x"] = dev(x) if x is not None else None
     return t

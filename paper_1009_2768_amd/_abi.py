@@ -10,6 +10,7 @@ HOMOG, SLAB1D = 1, 2
 FP64, FP32_MIXED = 1, 2
 NATURAL, FIXED, ADAPTIVE, ADAPTIVE_REUSE = 0, 1, 2, 3
 WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
+BC_SPECULAR, BC_INFLOW = 0, 1
 
 EINVAL, ENOMEM, ENOSPC, EIO, EOVERFLOW = -22, -12, -28, -5, -75
 CELL_OVERFLOW = 1
@@ -17,7 +18,7 @@ CELL_OVERFLOW = 1
 EXPORTS = [
     "trmc_abi_version", "trmc_strerror", "trmc_workspace_size", "trmc_ctx_workspace_size", "trmc_init",
     "trmc_step", "trmc_moments", "trmc_state", "trmc_read", "trmc_admit", "trmc_retire", "trmc_sync",
-    "trmc_destroy", "trmc_set_schedule", "trmc_get_schedule", "trmc_use_graph",
+    "trmc_destroy", "trmc_set_schedule", "trmc_get_schedule", "trmc_use_graph", "trmc_count",
 ]
 
 SCHED_BUCKETS = 32
@@ -35,6 +36,8 @@ class Desc(ctypes.Structure):
         ("step0", ctypes.c_uint32), ("delta1", ctypes.c_double), ("delta2", ctypes.c_double),
         ("m_state0", ctypes.POINTER(ctypes.c_uint32)),
         ("wb", ctypes.c_uint32), ("wb_mmax", ctypes.c_uint32),
+        ("bc", ctypes.c_uint32), ("n_live0", ctypes.c_uint32),
+        ("in_left", ctypes.c_double * 3), ("in_right", ctypes.c_double * 3),
     ]
 
 
@@ -108,6 +111,8 @@ def load():
     L.trmc_get_schedule.restype = i
     L.trmc_use_graph.argtypes = [vp, i]
     L.trmc_use_graph.restype = i
+    L.trmc_count.argtypes = [vp, u32, P(ctypes.c_uint64)]
+    L.trmc_count.restype = i
     _lib = L
     return L
 

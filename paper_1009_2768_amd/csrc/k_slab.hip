@@ -58,6 +58,26 @@ __device__ __forceinline__ uint32_t slab_move<float>(float& x, float& v, float d
     return cf < 0.0 ? 0u : (cf >= (double)nc ? nc - 1u : (uint32_t)cf);
 }
 
+// Free flight out of an open slab: a particle beyond either end has left and
+// goes to the extra bucket nc.
+template <typename T>
+__device__ __forceinline__ uint32_t slab_move_open(T& x, T v, T dt, T L, double inv_dx, uint32_t nc)
+{
+#pragma clang fp contract(off)
+    const T xn = (T)fma(v, dt, x);
+    x = xn;
+    if (xn < T(0) || xn > L) return nc;
+    const double cf = floor((double)xn * inv_dx);
+    return cf >= (double)nc ? nc - 1u : (uint32_t)cf;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t slab_step(const InstDev* I, T& x, T& v, T dt, T L, double inv_dx, uint32_t nc,
+                                              bool open)
+{
+    return open ? slab_move_open<T>(x, v, dt, L, inv_dx, nc) : slab_move<T>(x, v, dt, L, inv_dx, nc);
+}
+
 // Tile size used by the sort of an instance with n_cells cells: at least 4 cells'
 // worth of counters per particle... i.e. the dense histogram costs <= 1 byte per particle.
 __host__ __device__ inline uint32_t sort_tile(uint32_t n_cells)
@@ -78,11 +98,13 @@ __global__ __launch_bounds__(1024) void k_hist(const CellRef* __restrict__ slabs
     tile_of(prefix, ns, blockIdx.x, b, kt);
     InstDev* __restrict__ I = slabs[b].inst;
     const uint32_t nc = I->n_cells;
+    const bool open = I->bc != 0u;
+    const uint32_t nb = nc + (open ? 1u : 0u);  // open slab: bucket nc holds the particles that left
     const uint32_t tile = sort_tile(nc);
-    const uint64_t n = I->n;
+    const uint64_t n = I->n_live;
     const uint64_t t0 = (uint64_t)kt * tile;
     const uint64_t t1 = (t0 + tile < n) ? t0 + tile : n;
-    for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) hist[c] = 0;
+    for (uint32_t c = threadIdx.x; c < nb; c += blockDim.x) hist[c] = 0;
     __syncthreads();
     const uint32_t cur = I->cur;
     const T* __restrict__ x = reinterpret_cast<const T*>(I->x[cur]);
@@ -91,12 +113,12 @@ __global__ __launch_bounds__(1024) void k_hist(const CellRef* __restrict__ slabs
     const double inv_dx = I->inv_dx;
     for (uint64_t p = t0 + threadIdx.x; p < t1; p += blockDim.x) {
         T xp = x[p], vp = vx[p];
-        const uint32_t c = slab_move<T>(xp, vp, dt, L, inv_dx, nc);
+        const uint32_t c = slab_step<T>(I, xp, vp, dt, L, inv_dx, nc, open);
         atomicAdd(&hist[c], 1u);
     }
     __syncthreads();
-    uint32_t* out = I->hist + (uint64_t)kt * nc;
-    for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) out[c] = hist[c];
+    uint32_t* out = I->hist + (uint64_t)kt * nb;
+    for (uint32_t c = threadIdx.x; c < nb; c += blockDim.x) out[c] = hist[c];
 }
 
 // Column scan over tiles: hist[t][c] <- sum_{t' < t} hist[t'][c]; totals to
@@ -107,13 +129,13 @@ __global__ __launch_bounds__(256) void k_scan_tiles(const CellRef* __restrict__ 
     uint32_t b, kb;
     tile_of(prefix, ns, blockIdx.x, b, kb);
     InstDev* __restrict__ I = slabs[b].inst;
-    const uint32_t nc = I->n_cells;
+    const uint32_t nb = I->n_cells + (I->bc != 0u ? 1u : 0u);
     const uint32_t c = kb * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
+    if (c >= nb) return;
     const uint32_t nt = I->n_tiles;
     uint32_t acc = 0;
     for (uint32_t t = 0; t < nt; ++t) {
-        uint32_t* h = I->hist + (uint64_t)t * nc + c;
+        uint32_t* h = I->hist + (uint64_t)t * nb + c;
         const uint32_t v = *h;
         *h = acc;
         acc += v;
@@ -126,7 +148,7 @@ __global__ __launch_bounds__(1024) void k_scan_cells(const CellRef* __restrict__
 {
     __shared__ uint32_t part[1024];
     InstDev* __restrict__ I = slabs[blockIdx.x].inst;
-    const uint32_t nc = I->n_cells;
+    const uint32_t nc = I->n_cells + (I->bc != 0u ? 1u : 0u);  // buckets (open slab: + the leavers)
     const uint32_t per = (nc + 1023u) / 1024u;
     const uint32_t b = threadIdx.x * per;
     const uint32_t e = (b + per < nc) ? b + per : nc;
@@ -148,6 +170,10 @@ __global__ __launch_bounds__(1024) void k_scan_cells(const CellRef* __restrict__
         I->cell_off[c + 1] = run;
     }
     if (threadIdx.x == 0) I->cell_off[0] = 0u;
+    if (I->bc != 0u) {
+        __syncthreads();
+        if (threadIdx.x == 0) I->n_next = I->cell_off[I->n_cells];  // particles still in the slab
+    }
 }
 
 template <typename T>
@@ -163,12 +189,14 @@ __global__ __launch_bounds__(1024) void k_scatter(const CellRef* __restrict__ sl
     tile_of(prefix, ns, blockIdx.x, b, kt);
     InstDev* __restrict__ I = slabs[b].inst;
     const uint32_t nc = I->n_cells;
+    const bool open = I->bc != 0u;
+    const uint32_t nb = nc + (open ? 1u : 0u);
     const uint32_t tile = sort_tile(nc);
-    const uint64_t n = I->n;
+    const uint64_t n = I->n_live;
     const uint64_t t0 = (uint64_t)kt * tile;
     const uint64_t t1 = (t0 + tile < n) ? t0 + tile : n;
-    const uint32_t* base = I->hist + (uint64_t)kt * nc;
-    for (uint32_t c = threadIdx.x; c < nc; c += blockDim.x) run[c] = I->cell_off[c] + base[c];
+    const uint32_t* base = I->hist + (uint64_t)kt * nb;
+    for (uint32_t c = threadIdx.x; c < nb; c += blockDim.x) run[c] = I->cell_off[c] + base[c];
     __syncthreads();
     const uint32_t cur = I->cur, nxt = cur ^ 1u;
     const T* __restrict__ x = reinterpret_cast<const T*>(I->x[cur]);
@@ -193,7 +221,7 @@ __global__ __launch_bounds__(1024) void k_scatter(const CellRef* __restrict__ sl
             vp = vx[p];
             wy = vy[p];
             wz = vz[p];
-            c = slab_move<T>(xp, vp, dt, L, inv_dx, nc);
+            c = slab_step<T>(I, xp, vp, dt, L, inv_dx, nc, open);
         }
         // distinct cells of the wave, in lane order of first appearance
         bool pend = valid;
@@ -239,6 +267,88 @@ __global__ __launch_bounds__(1024) void k_scatter(const CellRef* __restrict__ sl
         __syncthreads();
         (void)nw;
     }
+}
+
+
+// ---------------------------------------------------------------------------
+// Open slab (stationary shock, Sec. 5.2): each end is a Maxwellian reservoir.
+// Per step, before transport, end e injects floor(lambda_e + U) particles,
+// lambda_e the expected number crossing inward in dt.  The inward normal speed
+// over sigma inverts the flux-weighted half-range law, density w phi(w - a) on
+// w > 0, whose distribution function has the closed form
+//   F(w) = phi(a) - phi(w - a) + a (Phi(w - a) - Phi(-a)),  F(inf) = phi(a) + a Phi(a),
+// by 64 bisection steps; the tangential speeds are Maxwellian; the particle is
+// placed outside by the part of the step it has not yet flown, so the transport
+// that follows brings it in.  Entries go after the live particles, left end
+// first.  Keys: cell field 0xFFFFFFF0 + end, tag INJ (count: index 0, aux 2;
+// particle i: index i, aux 0 and 1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double std_pdf(double t) { return exp(-0.5 * t * t) * 0.3989422804014327; }
+__device__ __forceinline__ double std_cdf(double t) { return 0.5 * erfc(-t / 1.4142135623730951); }
+
+__device__ __forceinline__ double flux_speed(double a, double u)
+{
+#pragma clang fp contract(off)
+    const double pa = std_pdf(a), ca = std_cdf(-a);
+    const double target = u * (pa + a * std_cdf(a));
+    double lo = 0.0, hi = (a > 0.0 ? a : 0.0) + 12.0;
+    for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const double F = (pa - std_pdf(mid - a)) + a * (std_cdf(mid - a) - ca);
+        if (F < target) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_inject(const CellRef* __restrict__ slabs, uint32_t ns)
+{
+    InstDev* __restrict__ I = slabs[blockIdx.x].inst;
+    if (I->bc == 0u) return;
+    __shared__ uint32_t cnt[2];
+    const uint32_t n = I->n_live, step = I->step;
+    if (threadIdx.x < 2u) {
+        const uint32_t e = threadIdx.x;
+        const Key key{I->seed, I->uid, 0xFFFFFFF0u + e, step};
+        const uint4 w = draw(key, 0, TAG_INJ, 2);
+        const double k = floor(I->in_lam[e] + u53(w.x, w.y));
+        cnt[e] = k < 4294967295.0 ? (uint32_t)k : 0xFFFFFFFFu;  // a huge count fails the capacity test
+    }
+    __syncthreads();
+    const uint32_t kl = cnt[0], kr = cnt[1];
+    if ((uint64_t)n + kl + kr > I->n) {  // arrays full: nothing enters, the step is flagged
+        if (threadIdx.x == 0) atomicOr(I->error, INJECT_FULL);
+        return;
+    }
+    const uint32_t cur = I->cur;
+    T* __restrict__ x = reinterpret_cast<T*>(I->x[cur]);
+    T* __restrict__ vx = reinterpret_cast<T*>(I->vx[cur]);
+    T* __restrict__ vy = reinterpret_cast<T*>(I->vy[cur]);
+    T* __restrict__ vz = reinterpret_cast<T*>(I->vz[cur]);
+    const double dt = I->dt, L = I->length;
+    for (uint32_t j = threadIdx.x; j < kl + kr; j += blockDim.x) {
+#pragma clang fp contract(off)
+        const uint32_t e = j < kl ? 0u : 1u;
+        const uint32_t i = j < kl ? j : j - kl;
+        const Key key{I->seed, I->uid, 0xFFFFFFF0u + e, step};
+        const uint4 b0 = draw(key, i, TAG_INJ, 0);
+        const uint4 b1 = draw(key, i, TAG_INJ, 1);
+        const double u0 = u53(b0.x, b1.x), u1 = u53(b0.y, b1.y), u2 = u53(b0.z, b1.z), u3 = u53(b0.w, b1.w);
+        const double sig = I->in_sig[e];
+        const double vn = sig * flux_speed(I->in_a[e], u0);
+        const double v = e == 0u ? vn : -vn;
+        const double r = sqrt(-2.0 * log(1.0 - u2));
+        double sn, cs;
+        sincos(6.283185307179586 * u3, &sn, &cs);
+        const uint64_t at = (uint64_t)n + j;
+        x[at] = (T)(e == 0u ? -v * dt * u1 : L - v * dt * u1);
+        vx[at] = (T)v;
+        vy[at] = (T)(sig * (r * cs));
+        vz[at] = (T)(sig * (r * sn));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) I->n_live = n + kl + kr;
 }
 
 // Per-cell moments (FP64): rho, u, T, P_xx, P_yy, P_zz, M4 per unit mass.
@@ -297,7 +407,10 @@ __global__ void k_advance(InstDev* const* __restrict__ insts, uint32_t n_inst)
     if (i >= n_inst) return;
     InstDev* I = insts[i];
     I->step += 1u;
-    if (I->geometry == GEOM_SLAB) I->cur ^= 1u;
+    if (I->geometry == GEOM_SLAB) {
+        I->cur ^= 1u;
+        if (I->bc != 0u) I->n_live = I->n_next;
+    }
 }
 
 template __global__ void k_hist<float>(const CellRef*, const uint32_t*, uint32_t);
@@ -305,6 +418,8 @@ template __global__ void k_hist<double>(const CellRef*, const uint32_t*, uint32_
 template __global__ void k_scatter<float>(const CellRef*, const uint32_t*, uint32_t);
 template __global__ void k_scatter<double>(const CellRef*, const uint32_t*, uint32_t);
 template __global__ void k_moments<float>(const CellRef*, uint32_t);
+template __global__ void k_inject<float>(const CellRef*, uint32_t);
+template __global__ void k_inject<double>(const CellRef*, uint32_t);
 template __global__ void k_moments<double>(const CellRef*, uint32_t);
 
 }  // namespace trmc

@@ -19,6 +19,8 @@ __global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, ui
 template <typename T>
 __global__ void k_collide_wb(const CellRef*, uint32_t, uint32_t);
 template <typename T>
+__global__ void k_inject(const CellRef*, uint32_t);
+template <typename T>
 __global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
 template <typename T>
 __global__ void k_hist(const CellRef*, const uint32_t*, uint32_t);
@@ -79,7 +81,7 @@ Layout layout_of(const trmc_desc& d)
     L.inst = p;    p += al(sizeof(InstDev));
     L.refs = p;    p += al(sizeof(CellRef) * nc);
     L.eps = p;     p += al(sizeof(double) * nc);
-    L.off = p;     p += al(sizeof(uint32_t) * (nc + 1));
+    L.off = p;     p += al(sizeof(uint32_t) * (nc + 2));  // + the open slab's bucket of leavers
     L.mstate = p;  p += al(sizeof(uint32_t) * nc);
     L.stats = p;   p += al(sizeof(CellStats) * nc);
     L.mom = p;     p += al(sizeof(double) * 9 * nc);
@@ -87,7 +89,7 @@ Layout layout_of(const trmc_desc& d)
     if (d.geometry == TRMC_SLAB1D) {
         const uint32_t tile = sort_tile_h(nc);
         L.n_tiles = (uint32_t)((n + tile - 1) / tile);
-        L.hist = p;  p += al(sizeof(uint32_t) * (size_t)L.n_tiles * nc);
+        L.hist = p;  p += al(sizeof(uint32_t) * (size_t)L.n_tiles * (nc + 1));
         L.bx = p;    p += al(sz * n);
         L.bvx = p;   p += al(sz * n);
         L.bvy = p;   p += al(sz * n);
@@ -128,6 +130,16 @@ int validate(const trmc_desc* d)
     if (d->m_init < 1 || d->m_init > d->m_cap) return TRMC_EINVAL;
     if (d->trunc >= TRMC_ADAPTIVE && !(d->delta1 > 0.0 && d->delta1 < d->delta2)) return TRMC_EINVAL;
     if (d->wb > TRMC_WB_MEAN) return TRMC_EINVAL;
+    if (d->bc > TRMC_BC_INFLOW || (d->bc == TRMC_BC_INFLOW && d->geometry != TRMC_SLAB1D)) return TRMC_EINVAL;
+    if (d->bc == TRMC_BC_INFLOW) {
+        for (const double* st : {d->in_left, d->in_right})
+            if (!(st[0] > 0.0) || !(st[2] > 0.0) || !std::isfinite(st[0]) || !std::isfinite(st[1]) ||
+                !std::isfinite(st[2]))
+                return TRMC_EINVAL;
+        if (d->n_live0 > d->n_particles) return TRMC_EINVAL;
+    } else if (d->n_live0 != 0 && d->n_live0 != d->n_particles) {
+        return TRMC_EINVAL;
+    }
     if (d->wb != TRMC_WB_OFF && (d->trunc >= TRMC_ADAPTIVE || d->wb_mmax < 1)) return TRMC_EINVAL;
     if (d->m_state0) {
         for (uint32_t c = 0; c < nc; ++c)
@@ -271,8 +283,8 @@ int rebuild_tables(trmc_ctx* c)
         const int k = s.host.precision == PREC_FP64 ? 1 : 0;
         sref[k].push_back(CellRef{s.dev, 0, 0});
         tpre[k].push_back(tpre[k].back() + s.lay.n_tiles);
-        cpre[k].push_back(cpre[k].back() + (s.host.n_cells + 255u) / 256u);
-        c->slab_maxnc[k] = std::max(c->slab_maxnc[k], s.host.n_cells);
+        cpre[k].push_back(cpre[k].back() + (s.host.n_cells + 1u + 255u) / 256u);
+        c->slab_maxnc[k] = std::max(c->slab_maxnc[k], s.host.n_cells + 1u);
     }
     for (int k = 0; k < 2; ++k) {
         c->n_slab[k] = (uint32_t)sref[k].size();
@@ -298,6 +310,26 @@ int rebuild_tables(trmc_ctx* c)
     c->graph_dirty = true;
     // the host vectors die here: make the copies complete first
     return hip_status(hipStreamSynchronize(c->stream));
+}
+
+// Reservoir constants of an open slab (the same closed forms as the CPU check,
+// with contraction off, so that the mean number of entries has identical bits):
+// sigma = sqrt(T), a = inward drift / sigma, lambda = (rho / weight) sigma
+// (phi(a) + a Phi(a)) dt.
+void reservoirs(const trmc_desc& d, InstDev& h)
+{
+#pragma clang fp contract(off)
+    for (int e = 0; e < 2; ++e) {
+        const double* st = e == 0 ? d.in_left : d.in_right;
+        const double sigma = std::sqrt(st[2]);
+        const double u_in = e == 0 ? st[1] : -st[1];
+        const double a = u_in / sigma;
+        const double phi = std::exp(-0.5 * a * a) * 0.3989422804014327;
+        const double Phi = 0.5 * std::erfc(-a / std::sqrt(2.0));
+        h.in_sig[e] = sigma;
+        h.in_a[e] = a;
+        h.in_lam[e] = st[0] / d.particle_weight * sigma * (phi + a * Phi) * d.dt;
+    }
 }
 
 int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned char* ws, size_t bytes,
@@ -347,6 +379,10 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
         h.vz[1] = b->vz;
     }
     h.n = d->n_particles;
+    h.bc = d->bc;
+    h.n_live = d->bc == TRMC_BC_INFLOW ? d->n_live0 : (uint32_t)d->n_particles;
+    h.n_next = h.n_live;
+    if (d->bc == TRMC_BC_INFLOW) reservoirs(*d, h);
     h.n_cells = nc;
     h.geometry = d->geometry == TRMC_SLAB1D ? GEOM_SLAB : GEOM_HOMOG;
     h.precision = d->precision == TRMC_FP64 ? PREC_FP64 : PREC_FP32;
@@ -383,21 +419,22 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     h.bigstate = d->geometry == TRMC_SLAB1D ? nullptr : ws + L.big;
 
     std::vector<double> eps(nc);
-    std::vector<uint32_t> off(nc + 1, 0), ms(nc);
+    std::vector<uint32_t> off(nc + 2, 0), ms(nc);
     std::vector<CellRef> refs(nc);
     for (uint32_t i = 0; i < nc; ++i) {
         eps[i] = d->eps_cells ? d->eps_cells[i] : d->eps;
         ms[i] = d->m_state0 ? d->m_state0[i] : d->m_init;
         refs[i] = CellRef{s.dev, i, 0};
     }
-    off[nc] = (uint32_t)d->n_particles;  // homogeneous: one cell [0, n); slab: set by the sort
+    off[nc] = h.n_live;  // homogeneous: one cell [0, n); slab: set by the sort
+    off[nc + 1] = h.n_live;
     hipError_t e = hipSuccess;
     e = e == hipSuccess ? hipMemcpyAsync(ws + L.inst, &h, sizeof(InstDev), hipMemcpyHostToDevice, c->stream) : e;
     e = e == hipSuccess ? hipMemcpyAsync(ws + L.refs, refs.data(), sizeof(CellRef) * nc, hipMemcpyHostToDevice,
                                          c->stream) : e;
     e = e == hipSuccess ? hipMemcpyAsync(ws + L.eps, eps.data(), sizeof(double) * nc, hipMemcpyHostToDevice,
                                          c->stream) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(ws + L.off, off.data(), sizeof(uint32_t) * (nc + 1),
+    e = e == hipSuccess ? hipMemcpyAsync(ws + L.off, off.data(), sizeof(uint32_t) * (nc + 2),
                                          hipMemcpyHostToDevice, c->stream) : e;
     e = e == hipSuccess ? hipMemcpyAsync(ws + L.mstate, ms.data(), sizeof(uint32_t) * nc, hipMemcpyHostToDevice,
                                          c->stream) : e;
@@ -427,6 +464,7 @@ int launch_slabs(trmc_ctx* c, int k)
     const uint32_t ns = c->n_slab[k];
     if (ns == 0 || c->slab_tiles[k] == 0) return 0;
     const size_t lds = sizeof(uint32_t) * c->slab_maxnc[k];
+    hipLaunchKernelGGL(k_inject<T>, dim3(ns), dim3(256), 0, c->stream, c->slab_refs[k], ns);
     hipLaunchKernelGGL(k_hist<T>, dim3(c->slab_tiles[k]), dim3(1024), lds, c->stream, c->slab_refs[k],
                        c->slab_tpre[k], ns);
     hipLaunchKernelGGL(k_scan_tiles, dim3(c->slab_cblk[k]), dim3(256), 0, c->stream, c->slab_refs[k],
@@ -730,7 +768,7 @@ int trmc_sync(trmc_ctx* c)
     if (err) {
         const uint32_t zero = 0;
         if (hipMemcpy(c->error, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return TRMC_EIO;
-        return TRMC_EOVERFLOW;
+        return (err & INJECT_FULL) ? TRMC_ENOSPC : TRMC_EOVERFLOW;
     }
     return c->sticky;
 }
@@ -811,8 +849,14 @@ int trmc_read(trmc_ctx* c, uint32_t slot, void* x, void* vx, void* vy, void* vz,
     Slot& s = c->slots[slot];
     trmc_particles cur{};
     trmc_state(c, slot, &cur);
-    const size_t bytes = (s.host.precision == PREC_FP64 ? 8 : 4) * s.host.n;
     int rc = trmc_sync(c);
+    uint64_t live = s.host.n;
+    if (s.host.bc != 0u) {
+        uint32_t nl = 0;
+        if (hipMemcpy(&nl, &s.dev->n_live, sizeof nl, hipMemcpyDeviceToHost) != hipSuccess) return c->sticky = TRMC_EIO;
+        live = nl;
+    }
+    const size_t bytes = (s.host.precision == PREC_FP64 ? 8 : 4) * live;
     hipError_t e = hipSuccess;
     if (x && s.host.geometry == GEOM_SLAB) e = e == hipSuccess ? hipMemcpy(x, cur.x, bytes, hipMemcpyDeviceToHost) : e;
     if (vx) e = e == hipSuccess ? hipMemcpy(vx, cur.vx, bytes, hipMemcpyDeviceToHost) : e;
@@ -823,6 +867,21 @@ int trmc_read(trmc_ctx* c, uint32_t slot, void* x, void* vx, void* vy, void* vz,
                                         hipMemcpyDeviceToHost) : e;
     if (step) *step = s.desc.step0 + (uint32_t)s.steps;
     if (e != hipSuccess) return c->sticky = TRMC_EIO;
+    return rc;
+}
+
+int trmc_count(trmc_ctx* c, uint32_t slot, uint64_t* n_live)
+{
+    if (!c || !n_live || slot >= c->slots.size() || !c->slots[slot].active) return TRMC_EINVAL;
+    const Slot& s = c->slots[slot];
+    const int rc = trmc_sync(c);
+    if (s.host.bc == 0u) {
+        *n_live = s.host.n;
+        return rc;
+    }
+    uint32_t nl = 0;
+    if (hipMemcpy(&nl, &s.dev->n_live, sizeof nl, hipMemcpyDeviceToHost) != hipSuccess) return c->sticky = TRMC_EIO;
+    *n_live = nl;
     return rc;
 }
 

@@ -13,7 +13,7 @@ namespace trmc {
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).  Key {seed, uid},
 // counter {index, tag << 24 | aux, cell, step}.
 // ---------------------------------------------------------------------------
-enum : uint32_t { TAG_SPLIT = 1, TAG_PERM = 2, TAG_TREE = 3, TAG_COLL = 4, TAG_MAXW = 5 };
+enum : uint32_t { TAG_SPLIT = 1, TAG_PERM = 2, TAG_TREE = 3, TAG_COLL = 4, TAG_MAXW = 5, TAG_INJ = 6 };
 
 struct Key {
     uint32_t seed, uid, cell, step;

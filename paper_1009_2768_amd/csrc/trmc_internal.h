@@ -10,7 +10,7 @@ enum : uint32_t { GEOM_HOMOG = 1, GEOM_SLAB = 2 };
 enum : uint32_t { PREC_FP64 = 1, PREC_FP32 = 2 };
 enum : uint32_t { TRUNC_NATURAL = 0, TRUNC_FIXED = 1, TRUNC_ADAPTIVE = 2, TRUNC_ADAPTIVE_REUSE = 3 };
 enum : uint32_t { WB_OFF = 0, WB_MIN = 1, WB_MEAN = 2 };  // tree-shape truncation (Sec. 4.4)
-enum : uint32_t { CELL_OVERFLOW = 1u };
+enum : uint32_t { CELL_OVERFLOW = 1u, INJECT_FULL = 2u };  // context error word bits
 
 constexpr uint32_t kMaxDepth = 2048;     // largest m_cap accepted
 constexpr uint32_t kMaxSlabCells = 12288;  // LDS histogram of the sort
@@ -47,6 +47,11 @@ struct InstDev {
     uint32_t step, cur;     // next step index; slab: buffer holding the state
     uint32_t n_tiles, pad0;
     uint32_t wb, wb_mmax;   // tree-shape truncation: WB_* and m_max
+    uint32_t bc;            // slab ends: 0 specular walls, 1 reservoirs (open slab)
+    uint32_t n_live;        // particles in the slab (open slab: changes every step; else n)
+    uint32_t n_next;        // open slab: particles left after this step's transport
+    uint32_t pad1;
+    double in_sig[2], in_a[2], in_lam[2];  // reservoirs: sqrt(T), inward drift / sqrt(T), mean entries per step
     double length, dt, rho_factor, alpha, delta1, delta2, inv_dx;
     const double* eps_cells;  // [n_cells]
     uint32_t* cell_off;       // [n_cells + 1]
