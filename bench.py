@@ -243,6 +243,53 @@ def tree_shape_truncation(T, n_inst, seed, steps=5):
     return out
 
 
+def stationary_shock(T, seed, steps=400, average_from=200):
+    """The paper's stationary shock (Sec. 5.2): Mach 3, 50 cells, 1000 upstream
+    particles per cell, reservoirs at both ends, hard spheres, adaptive depth, FP32.
+    For eps 1, 0.1 and 1e-3: time per step (graph replay), and the time-averaged
+    far-field density and temperature against the Rankine-Hugoniot states."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    nc = 50
+    x, vx, vy, vz, w, up, down, cap = W.shock(nc, 1000, seed=seed)
+    out = {"workload": "Mach-3 stationary shock, 50 cells x 1000 upstream particles per cell, reservoirs at both "
+                       "ends, hard spheres, adaptive depth, fp32", "steps": steps,
+           "rankine_hugoniot": {"rho": [up[0], down[0]], "T": [up[2], down[2]]}}
+    for eps in (1.0, 0.1, 1e-3):
+        inst = T.Instance(n_particles=cap, geometry=T.SLAB1D, n_cells=nc, length=1.0, dt=W.shock_dt(1.0, nc),
+                          eps=eps, alpha=1.0, trunc=T.ADAPTIVE, m_init=2, m_cap=64, particle_weight=w, uid=7000,
+                          seed=seed, precision=T.FP32_MIXED, bc=T.BC_INFLOW, n_live0=len(x), in_left=up,
+                          in_right=down)
+        parts = [T.device_particles(vx, vy, vz, x, T.FP32_MIXED, capacity=cap)]
+        ctx = T.Context([inst], parts)
+        ctx.use_graph(True)
+        ctx.step(average_from)
+        ctx.sync()
+        rho, temp, ps, wall = [], [], 0, 0.0
+        for s in range(steps - average_from):
+            n0 = ctx.count(0)
+            t0 = time.perf_counter()
+            ctx.step(1)
+            ctx.sync()
+            wall += time.perf_counter() - t0
+            ps += n0
+            if s % 4 == 0:
+                m = ctx.moments(0)
+                rho.append(m["rho"])
+                temp.append(m["T"])
+        ctx.close()
+        rho, temp = np.mean(rho, 0), np.mean(temp, 0)
+        out[f"eps_{eps:g}"] = {"ms_per_step": wall * 1e3 / (steps - average_from), "particle_steps_per_s": ps / wall,
+                               "rho_up": float(rho[:5].mean()), "rho_down": float(rho[-8:].mean()),
+                               "T_up": float(temp[:5].mean()), "T_down": float(temp[-8:].mean())}
+        log(f"stationary shock eps {eps:g}: {out[f'eps_{eps:g}']}")
+        del parts
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(T, args):
     """Serving run: a Poisson stream of homogeneous solves and shock tubes (N
     log-uniform in [1e3, 1e6], 50-500 steps, eps log-uniform in [1e-4, 1]) served
@@ -293,6 +340,7 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="HBM budget of the running requests")
     ap.add_argument("--no-reuse", action="store_true",
                     help="skip the run of the workload with the adaptive depth that keeps rejected attempts")
+    ap.add_argument("--no-shock", action="store_true", help="skip the stationary-shock run")
     ap.add_argument("--wb-instances", type=int, default=64,
                     help="instances of the tree-shape truncation comparison (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -406,6 +454,8 @@ def main():
         log("batched versus one instance at a time ...")
         line["batching"] = batching_speedup(T, N, eps, alpha, init, args.seed, prec, table, args.speedup_stride)
         log(f"batching: {line['batching']}")
+    if not args.no_shock:
+        line["stationary_shock"] = stationary_shock(T, args.seed)
     if args.wb_instances > 0:
         line["tree_shape_truncation"] = tree_shape_truncation(T, args.wb_instances, args.seed)
     if args.serve_seconds > 0:
