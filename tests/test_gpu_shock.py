@@ -119,3 +119,28 @@ def test_full_arrays_give_enospc(trmc):
         ctx.count(0)
     assert e.value.code == -28
     ctx.close()
+
+
+def test_open_slab_filling_from_empty_matches_oracle(trmc, orc):
+    """No particle at admission: the reservoirs fill the slab; counts exact and
+    states within the parity tolerance after 12 steps."""
+    T = trmc
+    up, down = W.shock_states()
+    nc, w, cap = 20, 1.0 / 20 / 200, 60000
+    e = np.zeros(0)
+    inst = T.Instance(n_particles=cap, geometry=T.SLAB1D, n_cells=nc, length=1.0, dt=W.shock_dt(1.0, nc), eps=0.1,
+                      alpha=1.0, trunc=T.ADAPTIVE, m_init=2, m_cap=64, particle_weight=w, uid=95, seed=4,
+                      precision=T.FP64, bc=T.BC_INFLOW, n_live0=0, in_left=up, in_right=down)
+    a = {"x": e, "vx": e, "vy": e, "vz": e}
+    say("open slab fp64 filling from empty, 12 steps")
+    parts = [T.device_particles(e, e, e, e, T.FP64, capacity=cap)]
+    ctx = T.Context([inst], parts)
+    o = oracle_of(orc, inst, a)
+    for s in range(12):
+        ctx.step(1)
+        o.run(1)
+        assert ctx.count(0) == o.n, f"step {s}"
+    got, mom = ctx.read(0), ctx.moments(0)
+    ctx.close()
+    assert o.n > 0
+    compare(o, got, mom, nc)
