@@ -305,7 +305,7 @@ def serving(T, args):
     log(f"serving schedule tuned in {time.time() - t0:.1f} s")
     done = srv.run(reqs, realtime=True)
     srv.close()
-    out = summarize(done, srv.wall)
+    out = summarize(done, srv.wall, srv.busy)
     out.update({"rate_per_s": args.serve_rate, "stream_s": args.serve_seconds,
                 "hbm_budget_gib": args.serve_budget_gib, "peak_hbm_gib": srv.peak_bytes / 2**30,
                 "peak_running": srv.peak_active, "ticks": srv.ticks, "precision": "fp32",
@@ -313,7 +313,8 @@ def serving(T, args):
                 "mix": "homogeneous (Maxwell) and Sod tubes (hard spheres) 50/50, N log-uniform [1e3, 1e6], "
                        "50-500 steps, eps log-uniform [1e-4, 1]"})
     log(f"serving: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
-        f"{out['particle_steps_per_s']:.3e} particle-steps/s, wall {srv.wall:.2f} s")
+        f"{out['particle_steps_per_s']:.3e} particle-steps/s, wall {srv.wall:.2f} s, device busy "
+        f"{srv.busy:.2f} s, HBM fraction {out['hbm_frac_wall']:.4f} (wall) {out['hbm_frac_busy']:.4f} (busy)")
     return out
 
 

@@ -188,7 +188,9 @@ int trmc_admit(trmc_ctx* ctx, const trmc_desc* desc, const trmc_particles* buf, 
                size_t workspace_bytes, uint32_t* slot);
 
 /* Remove instance `slot` from the active set (its memory is the caller's again
- * once the stream has passed this point). */
+ * once the stream has passed this point).  Admissions and retirements take
+ * effect at the next trmc_step, which rebuilds the work lists once for all of
+ * them. */
 int trmc_retire(trmc_ctx* ctx, uint32_t slot);
 
 /* Batching: the kernel path of each cell, chosen per bucket of the expected

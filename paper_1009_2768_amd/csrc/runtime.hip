@@ -192,6 +192,7 @@ struct trmc_ctx {
     // captured step: every launch of one step, replayed by trmc_step
     bool use_graph = false;
     bool graph_dirty = true;
+    bool tables_dirty = false;  // admissions or retirements since the work lists were built
     hipStream_t cap_stream = nullptr;  // stream the step is captured on
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -638,7 +639,11 @@ int trmc_admit(trmc_ctx* c, const trmc_desc* desc, const trmc_particles* buf, vo
                size_t workspace_bytes, uint32_t* slot)
 {
     if (!c || !slot) return TRMC_EINVAL;
-    return admit_one(c, desc, buf, reinterpret_cast<unsigned char*>(workspace), workspace_bytes, slot, true);
+    // the work lists are rebuilt once, at the next step, for all admissions and
+    // retirements since the last one
+    const int rc = admit_one(c, desc, buf, reinterpret_cast<unsigned char*>(workspace), workspace_bytes, slot, false);
+    if (!rc) c->tables_dirty = true;
+    return rc;
 }
 
 int trmc_retire(trmc_ctx* c, uint32_t slot)
@@ -647,7 +652,8 @@ int trmc_retire(trmc_ctx* c, uint32_t slot)
     Slot& s = c->slots[slot];
     s.active = false;
     c->cells_used -= s.host.n_cells;
-    return rebuild_tables(c);
+    c->tables_dirty = true;  // no step is enqueued for it from now on
+    return 0;
 }
 
 namespace {
@@ -712,6 +718,11 @@ int trmc_step(trmc_ctx* c, uint32_t n_steps)
     if (!c) return TRMC_EINVAL;
     if (c->sticky) return c->sticky;
     if (n_steps == 0) return 0;
+    if (c->tables_dirty) {
+        const int rc = rebuild_tables(c);
+        if (rc) return c->sticky = rc;
+        c->tables_dirty = false;
+    }
     if (c->use_graph && c->graph_dirty) {
         const int rc = capture_step(c);
         if (rc) return c->sticky = rc;

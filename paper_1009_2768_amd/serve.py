@@ -66,6 +66,7 @@ class Done:
     moments: dict = field(repr=False)
     state: dict | None = field(default=None, repr=False)
     tick_admitted: int = 0
+    bytes_per_step: int = 0  # algorithmic HBM bytes of one step: read and write of (x,) v
 
     @property
     def latency(self):
@@ -144,12 +145,16 @@ class Server:
         del self.active[slot]
         self.used -= nbytes
         self.cells -= int(req["n_cells"]) if req["slab"] else 1
-        return Done(req["rid"], int(req["n"]), int(req["steps"]), req["arrival"], t_adm, t, mom, state, tick)
+        sz = 4 if self.precision == FP32_MIXED else 8
+        per = (8 if req["slab"] else 6) * sz * int(req["n"])
+        return Done(req["rid"], int(req["n"]), int(req["steps"]), req["arrival"], t_adm, t, mom, state, tick, per)
 
     def run(self, requests, realtime: bool = True, log=None):
         """Serve the requests (sorted by arrival).  realtime: arrivals follow the
         wall clock (idle gaps are waited out); otherwise every request is queued
         at time 0.  Returns the list of Done records in completion order."""
+        import torch
+        ticks_ev = []  # (start, end) events of every tick on the context's stream
         pending = deque(sorted(requests, key=lambda r: r["arrival"]))
         waiting = deque()
         done = []
@@ -177,7 +182,11 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
                 continue
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record(self.ctx.stream)
             self.ctx.step(1)
+            ev[1].record(self.ctx.stream)
+            ticks_ev.append(ev)
             self.ticks += 1
             finished = []
             for slot, st in self.active.items():
@@ -190,16 +199,26 @@ class Server:
                 log(f"t={time.perf_counter() - t0:.3f}s tick {self.ticks}: {len(finished)} done, "
                     f"{len(self.active)} running, {len(waiting)} waiting, {self.used / 2**30:.2f} GiB")
         self.wall = time.perf_counter() - t0
+        self.ctx.sync()
+        self.busy = sum(a.elapsed_time(b) for a, b in ticks_ev) * 1e-3  # device time of the ticks, s
         return done
 
     def close(self):
         self.ctx.close()
 
 
-def summarize(done, wall):
+def summarize(done, wall, busy=None, peak_bytes_per_s=8e12):
+    """Latency percentiles, throughput, and the HBM roofline fraction of the
+    served work (algorithmic bytes: one read and one write of each particle per
+    step) over the wall time and over the device-busy time of the ticks."""
     lat = np.array([d.latency for d in done]) * 1e3
     ps = sum(d.n * d.steps for d in done)
-    return {"requests": len(done), "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
-            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
-            "mean_ms": float(lat.mean()) if len(lat) else None,
-            "particle_steps_per_s": ps / wall if wall > 0 else None, "particle_steps": ps, "wall_s": wall}
+    nbytes = float(sum(d.bytes_per_step * d.steps for d in done))
+    out = {"requests": len(done), "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+           "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+           "mean_ms": float(lat.mean()) if len(lat) else None,
+           "particle_steps_per_s": ps / wall if wall > 0 else None, "particle_steps": ps, "wall_s": wall,
+           "hbm_frac_wall": nbytes / wall / peak_bytes_per_s if wall > 0 else None}
+    if busy:
+        out.update({"device_busy_s": busy, "hbm_frac_busy": nbytes / busy / peak_bytes_per_s})
+    return out
