@@ -67,15 +67,18 @@ def build_context(T, N, eps, alpha, init, seed, precision, device="cuda", uids=N
     return ctx, (vx, vy, vz)
 
 
+# the sources the timed collision kernel is compiled from
+KERNEL_SOURCES = ("k_collide.hip", "collide_core.h", "trmc_device.h", "trmc_internal.h")
+
+
 def source_sha256() -> str:
-    """Hash of the kernel sources (names and contents), to tell whether stored
-    HBM counter figures still describe the kernels being timed."""
-    import glob
+    """Hash of the collision kernel's sources (names and contents), to tell whether
+    stored HBM counter figures still describe the kernel being timed."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1009_2768_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1009_2768_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
