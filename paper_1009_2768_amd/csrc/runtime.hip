@@ -194,6 +194,10 @@ struct trmc_ctx {
     bool graph_dirty = true;
     bool tables_dirty = false;  // admissions or retirements since the work lists were built
     hipStream_t cap_stream = nullptr;  // stream the step is captured on
+    // the tile pipeline of large homogeneous cells runs on a second stream, beside
+    // the slab sort and the whole-cell kernels (they touch different cells)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
@@ -477,10 +481,9 @@ int launch_slabs(trmc_ctx* c, int k)
 }
 
 
-// One collision step of every cell of precision k: the tiled pipeline for large
-// homogeneous cells, then the whole-cell kernel for the rest.
+// The tiled pipeline of the large homogeneous cells of precision k.
 template <typename T>
-int launch_collide(trmc_ctx* c, int k)
+int launch_tiled(trmc_ctx* c, int k)
 {
     const uint32_t nt = c->n_work[k][2];
     if (nt) {
@@ -501,6 +504,13 @@ int launch_collide(trmc_ctx* c, int k)
         hipLaunchKernelGGL(k_tile_zsum<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
         hipLaunchKernelGGL(k_tile_write<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
     }
+    return hip_status(hipGetLastError());
+}
+
+// The whole-cell kernels of precision k (every cell not on the tiled pipeline).
+template <typename T>
+int launch_whole(trmc_ctx* c, int k)
+{
     const uint32_t nb = c->n_work[k][0], ns = c->n_work[k][1];
     if (nb + ns) {
         const uint32_t small_blocks = (ns + kSmallPerBlock - 1) / kSmallPerBlock;
@@ -663,10 +673,23 @@ namespace {
 int enqueue_step(trmc_ctx* c, hipStream_t st)
 {
     const hipStream_t keep = c->stream;
-    c->stream = st;
     int rc = 0;
+    // fork: the tiled pipeline on the side stream, after everything before this step
+    const bool fork = c->side && (c->n_work[0][2] + c->n_work[1][2]) > 0;
+    if (fork) {
+        if (hipEventRecord(c->ev_fork, st) != hipSuccess || hipStreamWaitEvent(c->side, c->ev_fork, 0) != hipSuccess)
+            return TRMC_EIO;
+        c->stream = c->side;
+        for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_tiled<float>(c, 0) : launch_tiled<double>(c, 1);
+        if (!rc && hipEventRecord(c->ev_join, c->side) != hipSuccess) rc = TRMC_EIO;
+    }
+    c->stream = st;
+    if (!fork)
+        for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_tiled<float>(c, 0) : launch_tiled<double>(c, 1);
     for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_slabs<float>(c, 0) : launch_slabs<double>(c, 1);
-    for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_collide<float>(c, 0) : launch_collide<double>(c, 1);
+    for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_whole<float>(c, 0) : launch_whole<double>(c, 1);
+    // join before the step counters advance
+    if (fork && hipStreamWaitEvent(st, c->ev_join, 0) != hipSuccess && !rc) rc = TRMC_EIO;
     if (!rc && c->n_active)
         hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, st, c->inst_ptrs,
                            c->n_active);
@@ -685,6 +708,20 @@ void drop_graph(trmc_ctx* c)
 
 // Capture one step on the context's private stream (the caller's stream may be
 // the null stream, which cannot be captured).
+// The side stream and its two events (default priority), made once.
+int ensure_side(trmc_ctx* c)
+{
+    if (c->side) return 0;
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        c->side = nullptr;
+        return TRMC_EIO;
+    }
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        return TRMC_EIO;
+    return 0;
+}
+
 int capture_step(trmc_ctx* c)
 {
     if (c->graph_exec && hipStreamSynchronize(c->stream) != hipSuccess) return TRMC_EIO;
@@ -723,6 +760,7 @@ int trmc_step(trmc_ctx* c, uint32_t n_steps)
         if (rc) return c->sticky = rc;
         c->tables_dirty = false;
     }
+    if (const int rc = ensure_side(c)) return c->sticky = rc;
     if (c->use_graph && c->graph_dirty) {
         const int rc = capture_step(c);
         if (rc) return c->sticky = rc;
@@ -902,6 +940,10 @@ int trmc_destroy(trmc_ctx* c)
     const hipError_t e = hipStreamSynchronize(c->stream);
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
     return e == hipSuccess ? 0 : TRMC_EIO;
 }
