@@ -83,20 +83,67 @@ def source_sha256() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(kernel: str, table):
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_collide_batched_homogeneous_4096.traffic.json")
+
+
+def stored_traffic(kernel: str, table, steps_per_launch: int = 1):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or None when the
-    kernel sources differ from those the counters were taken with.  The caller
-    asks only when the step is that one kernel (no cell on the tile path)."""
-    path = os.path.join(ROOT, "profiles", "k_collide_batched_homogeneous_4096.traffic.json")
+    kernel sources differ from those the counters were taken with, or the counters
+    were taken on launches of another number of steps.  The caller asks only when
+    the step is that one kernel (no cell on the tile path)."""
     try:
-        with open(path) as fh:
+        with open(TRAFFIC_RECORD) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != source_sha256() or kernel not in rec.get("kernel", ""):
         return None
+    if int(rec.get("steps_per_launch", 1)) != steps_per_launch:
+        return None
     return rec["bytes_per_launch"]
+
+
+def time_steps(ctx, steps, warmup, fuse):
+    """`warmup` untimed steps, then exactly `steps` timed steps on the context's
+    stream, synchronised on both sides.  fuse: one call for all the timed steps
+    (each homogeneous cell goes through them in one launch, results identical to
+    single steps); else one call per step, replayed from the captured graph.
+    Returns the wall time of the timed steps (s) and the HIP-event time per step
+    (ms) measured on the library's stream."""
+    import numpy as np
+    import torch
+    ctx.fuse_steps(fuse)
+    stream = ctx.stream
+    if fuse:
+        ctx.step(warmup)
+    else:
+        for _ in range(warmup):
+            ctx.step(1)
+    ctx.sync()
+    torch.cuda.synchronize()
+    if fuse:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            ctx.step(steps)
+            e1.record(stream)
+        ctx.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, e0.elapsed_time(e1) / steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for k in range(steps):
+            ev[k][0].record(stream)
+            ctx.step(1)
+            ev[k][1].record(stream)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
 
 def cpu_baseline(N, eps, alpha, init, seed, budget_s=15.0):
@@ -174,35 +221,41 @@ def work_totals(T, ctx):
     return {"collisions": coll, "work_collisions": work, "cells_redone": redo}
 
 
-def adaptive_reuse(T, N, eps, alpha, init, seed, prec, table, steps, warmup):
+def adaptive_reuse(T, N, eps, alpha, init, seed, prec, table, steps, warmup, fuse):
     """The benchmark workload with the adaptive depth that keeps rejected attempts
     (Sec. 4.3, the collisions of the wrong depth reused) instead of recomputing
     them: same instances, schedule and timing."""
-    import numpy as np
     import torch
     ctx, bufs = build_context(T, N, eps, alpha, init, seed, prec, trunc=T.ADAPTIVE_REUSE)
     ctx.set_schedule(table)
     ctx.use_graph(True)
-    for _ in range(warmup):
-        ctx.step(1)
-    ctx.sync()
-    stream = ctx.stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for s in range(steps):
-            ev[s][0].record(stream)
-            ctx.step(1)
-            ev[s][1].record(stream)
-    ctx.sync()
-    wall = time.perf_counter() - t0
-    out = {"ms_per_step": wall * 1e3 / steps, "kernel_ms": float(np.mean([a.elapsed_time(b) for a, b in ev])),
+    wall, kernel_ms = time_steps(ctx, steps, warmup, fuse)
+    out = {"ms_per_step": wall * 1e3 / steps, "kernel_ms": kernel_ms,
            "particle_steps_per_s": int(N.sum()) * steps / wall}
     out.update(work_totals(T, ctx))
     ctx.close()
     del ctx, bufs
     torch.cuda.empty_cache()
     return out
+
+
+def step_fusion(T, N, eps, alpha, init, seed, prec, table, steps, warmup, fused_ms):
+    """The timed steps again, on a twin context (same inputs, same warmup, so the
+    same steps), one launch per step replayed from the captured graph instead of
+    one launch for all of them."""
+    import torch
+    ctx, bufs = build_context(T, N, eps, alpha, init, seed, prec)
+    ctx.set_schedule(table)
+    ctx.use_graph(True)
+    ctx.fuse_steps(False)
+    for _ in range(warmup):
+        ctx.step(1)
+    wall, kernel_ms = time_steps(ctx, steps, 0, False)
+    ctx.close()
+    del ctx, bufs
+    torch.cuda.empty_cache()
+    return {"fused_ms_per_step": fused_ms, "unfused_ms_per_step": wall * 1e3 / steps,
+            "unfused_kernel_ms": kernel_ms, "speedup": wall * 1e3 / steps / fused_ms}
 
 
 def tree_shape_truncation(T, n_inst, seed, steps=5):
@@ -336,6 +389,10 @@ def main():
     ap.add_argument("--table", default=None,
                     help="fixed schedule instead of tuning, e.g. 8:wave,9:wave,11:group (bucket:path)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one instead of a HIP graph")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="one launch per step instead of one launch taking every cell through all timed steps")
+    ap.add_argument("--no-fuse-compare", action="store_true",
+                    help="skip the timing of the same steps one launch per step on a twin context")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the Poisson request stream of the serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
@@ -394,32 +451,18 @@ def main():
     schedule = dict(sorted(schedule.items(), key=lambda kv: int(kv[0][2:])))
     if not args.no_graph:
         ctx.use_graph(True)
-    stream = ctx.stream
-    for s in range(args.warmup):
-        ctx.step(1)
-    ctx.sync()
-    log("warmup done")
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t_wall = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for s in range(args.steps):
-            ev[s][0].record(stream)
-            ctx.step(1)
-            ev[s][1].record(stream)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    step_ms = [a.elapsed_time(b) for a, b in ev]
+    fuse = not args.no_fuse
+    wall, avg_ms = time_steps(ctx, args.steps, args.warmup, fuse)
     ms_per_step = wall * 1000.0 / args.steps
     value = total * args.steps / wall
     sz = 4 if prec == T.FP32_MIXED else 8
     algo_bytes = 6 * sz * total  # one read and one write of (vx, vy, vz) per particle-step
-    avg_ms = float(np.mean(step_ms))
-    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
+    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9  # per step; a fused launch is `steps` steps
     kernel = "k_collide<float>" if prec == T.FP32_MIXED else "k_collide<double>"
     tiled = any(table[T.size_bucket(i)] in (0, 3) for i in ctx.instances)
-    traffic = None if tiled else stored_traffic(kernel, table)
+    fuse = fuse and not tiled  # a cell on the tile pipeline keeps one launch sequence per step
+    per_launch = args.steps if fuse else 1
+    traffic = None if tiled else stored_traffic(kernel, table, per_launch)
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, kernel events {avg_ms:.3f} ms")
     line = {
         "metric": "particle-collision-step updates/sec",
@@ -438,9 +481,11 @@ def main():
                                "eps log-uniform [1e-4, 10], Maxwell/hard-sphere 50/50, adaptive depth m_cap 64, "
                                "dt 0.05",
                    "instances": args.instances, "particles": total, "precision": args.precision,
-                   "schedule": schedule, "graph": not args.no_graph},
+                   "schedule": schedule, "graph": not args.no_graph, "fused_steps": fuse},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_schedule": json.load(open(TRAFFIC_RECORD))["table"] if traffic else None,
+                     "steps_per_launch": per_launch,
                      "kernel": (kernel + " (+ k_advance, about 4 us)") if not tiled else
                      "tile pipeline + " + kernel + " (several kernels per step)"},
     }
@@ -448,9 +493,14 @@ def main():
     ctx.close()
     del ctx, bufs
     torch.cuda.empty_cache()
+    if fuse and not args.no_fuse_compare:
+        log("the same steps, one launch per step ...")
+        line["step_fusion"] = step_fusion(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup,
+                                          ms_per_step)
+        log(f"step fusion: {line['step_fusion']}")
     if not args.no_reuse:
         log("adaptive depth keeping rejected attempts ...")
-        reuse = adaptive_reuse(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup)
+        reuse = adaptive_reuse(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup, fuse)
         line["adaptive_reuse"] = {"recompute": dict(ms_per_step=ms_per_step, kernel_ms=avg_ms, **recompute_work),
                                   "reuse": reuse, "speedup": ms_per_step / reuse["ms_per_step"]}
         log(f"adaptive reuse: {line['adaptive_reuse']}")

@@ -156,7 +156,12 @@ int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trm
               void* hip_stream);
 
 /* Advance every active instance by n_steps steps (transport, sort, collisions),
- * asynchronously on the context's stream. */
+ * asynchronously on the context's stream.  When every active instance is
+ * space-homogeneous and no cell is on the TILED path, and step fusion is on
+ * (trmc_fuse_steps, the default), n_steps > 1 runs as one launch per collision
+ * kernel in which each cell goes through the n_steps steps back to back (a
+ * homogeneous cell's step reads nothing but its own previous step); the results
+ * are identical to n_steps single steps. */
 int trmc_step(trmc_ctx* ctx, uint32_t n_steps);
 
 /* Moments and counters of instance `slot`, one entry per cell (cap >= n_cells).
@@ -214,6 +219,11 @@ int trmc_get_schedule(const trmc_ctx* ctx, uint32_t* paths, uint32_t n_buckets);
  * (captured on first use after the work tables change); on == 0: launches each
  * kernel directly.  Both enqueue the same kernels with the same arguments. */
 int trmc_use_graph(trmc_ctx* ctx, int on);
+
+/* on != 0 (the default): trmc_step fuses the steps of a call when it can (see
+ * trmc_step); on == 0: one step after another, each its own launches (or graph
+ * replay).  Results do not depend on it. */
+int trmc_fuse_steps(trmc_ctx* ctx, int on);
 
 /* Wait for the stream and report any asynchronous error. */
 int trmc_sync(trmc_ctx* ctx);

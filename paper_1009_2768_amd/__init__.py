@@ -199,6 +199,10 @@ class Context:
         """Replay one captured HIP graph per step instead of launching each kernel."""
         check(self._lib.trmc_use_graph(self._ctx, 1 if on else 0), "trmc_use_graph")
 
+    def fuse_steps(self, on: bool = True):
+        """Let step(n) take homogeneous cells through all n steps in one launch (the default)."""
+        check(self._lib.trmc_fuse_steps(self._ctx, 1 if on else 0), "trmc_fuse_steps")
+
     # -- serving -----------------------------------------------------------
     def admit(self, inst: Instance, particles: dict) -> int:
         import torch

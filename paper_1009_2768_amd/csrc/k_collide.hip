@@ -67,9 +67,12 @@ __device__ unsigned long long g_maxcell[12];
 
 constexpr int kUnroll = 2;
 
+// One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
+// it once per step, and inlined into their step loops the compiler keeps
+// per-step values live across the whole loop and spills them.
 template <typename T, int NT, int G, bool WB = false, bool REUSE = false>
-__device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, uint32_t n_work, uint32_t blk,
-                                              uint32_t lv_stride)
+__device__ __attribute__((noinline)) void collide_cells(const CellRef* __restrict__ work, uint32_t n_work, uint32_t blk,
+                                              uint32_t lv_stride, uint32_t soff)
 {
     constexpr int NGRP = NT / G;  // groups per workgroup
     extern __shared__ uint32_t lds_levels[];
@@ -91,7 +94,7 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
     const gptr<T> vy = as_global(uni(reinterpret_cast<T*>(I->vy[buf]) + off));
     const gptr<T> vz = as_global(uni(reinterpret_cast<T*>(I->vz[buf]) + off));
     CellStats* st = I->stats + cell;
-    const Key key = uni(Key{I->seed, I->uid, cell, I->step});
+    const Key key = uni(Key{I->seed, I->uid, cell, I->step + soff});  // step soff of this launch
 
 #ifndef TRMC_PRIO_CELL
 #define TRMC_PRIO_CELL 16384u
@@ -498,15 +501,28 @@ __device__ __forceinline__ void collide_cells(const CellRef* __restrict__ work, 
 }
 
 // Cells of the workgroup-per-cell list occupy the first n_big workgroups, cells
-// of the wave-per-cell list (eight per workgroup) the rest.
+// of the wave-per-cell list (eight per workgroup) the rest.  Each group takes
+// its cell through nsteps consecutive steps (nsteps > 1 only for homogeneous
+// instances, whose cells depend on nothing but themselves); the group's
+// barrier orders one step's stores before the next step's loads.
 template <typename T, bool REUSE = false>
 __device__ __forceinline__ void collide_entry(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big,
-                                              const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small)
+                                              const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small,
+                                              uint32_t nsteps)
 {
-    if (blockIdx.x < n_big)
-        collide_cells<T, kCollideThreads, kCollideThreads, false, REUSE>(big, n_big, blockIdx.x, lv_big);
-    else
-        collide_cells<T, kCollideThreads, 64, false, REUSE>(small, n_small, blockIdx.x - n_big, lv_small);
+    for (uint32_t s = 0; s < nsteps; ++s) {
+        // an opaque copy of the block index: the cell's loads are made again in
+        // every step instead of being kept live across the steps
+        uint32_t b = blockIdx.x;
+        asm volatile("" : "+s"(b));
+        if (b < n_big) {
+            collide_cells<T, kCollideThreads, kCollideThreads, false, REUSE>(big, n_big, b, lv_big, s);
+            gsync<kCollideThreads>();
+        } else {
+            collide_cells<T, kCollideThreads, 64, false, REUSE>(small, n_small, b - n_big, lv_small, s);
+            gsync<64>();
+        }
+    }
 }
 
 // The per-cell chains are latency bound, so resident waves matter: the FP32
@@ -516,56 +532,63 @@ __device__ __forceinline__ void collide_entry(const CellRef* __restrict__ big, u
 #define TRMC_F32_WAVES_PER_EU 6
 #endif
 template <typename T>
-__global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
+__global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t, uint32_t);
 
 template <>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(TRMC_F32_WAVES_PER_EU, 8))) void
 k_collide<float>(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big, const CellRef* __restrict__ small,
-                 uint32_t n_small, uint32_t lv_small)
+                 uint32_t n_small, uint32_t lv_small, uint32_t nsteps)
 {
-    collide_entry<float>(big, n_big, lv_big, small, n_small, lv_small);
+    collide_entry<float>(big, n_big, lv_big, small, n_small, lv_small, nsteps);
 }
 
 // Cells of instances with tree-shape truncation: one workgroup per cell.
 template <typename T>
 __global__ __launch_bounds__(kCollideThreads) void k_collide_wb(const CellRef* __restrict__ work, uint32_t n_work,
-                                                                uint32_t lv_stride)
+                                                                uint32_t lv_stride, uint32_t nsteps)
 {
-    collide_cells<T, kCollideThreads, kCollideThreads, true>(work, n_work, blockIdx.x, lv_stride);
+    for (uint32_t s = 0; s < nsteps; ++s) {
+        uint32_t b = blockIdx.x;
+        asm volatile("" : "+s"(b));  // per-step loads stay inside the loop
+        collide_cells<T, kCollideThreads, kCollideThreads, true>(work, n_work, b, lv_stride, s);
+        gsync<kCollideThreads>();
+    }
 }
-template __global__ void k_collide_wb<float>(const CellRef*, uint32_t, uint32_t);
-template __global__ void k_collide_wb<double>(const CellRef*, uint32_t, uint32_t);
+template __global__ void k_collide_wb<float>(const CellRef*, uint32_t, uint32_t, uint32_t);
+template __global__ void k_collide_wb<double>(const CellRef*, uint32_t, uint32_t, uint32_t);
 
 // Cells of instances with the adaptive depth that keeps rejected attempts, on
 // the same two paths as k_collide (dynamic LDS per group: level arrays, then
 // the draw offsets of each group).
 template <typename T>
-__global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
+__global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t, uint32_t);
 
 template <>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(TRMC_F32_WAVES_PER_EU, 8))) void
 k_collide_reuse<float>(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big,
-                       const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small)
+                       const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small, uint32_t nsteps)
 {
-    collide_entry<float, true>(big, n_big, lv_big, small, n_small, lv_small);
+    collide_entry<float, true>(big, n_big, lv_big, small, n_small, lv_small, nsteps);
 }
 
 template <>
 __global__ __launch_bounds__(kCollideThreads) void k_collide_reuse<double>(const CellRef* __restrict__ big,
                                                                            uint32_t n_big, uint32_t lv_big,
                                                                            const CellRef* __restrict__ small,
-                                                                           uint32_t n_small, uint32_t lv_small)
+                                                                           uint32_t n_small, uint32_t lv_small,
+                                                                           uint32_t nsteps)
 {
-    collide_entry<double, true>(big, n_big, lv_big, small, n_small, lv_small);
+    collide_entry<double, true>(big, n_big, lv_big, small, n_small, lv_small, nsteps);
 }
 
 template <>
 __global__ __launch_bounds__(kCollideThreads) void k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,
                                                                      uint32_t lv_big,
                                                                      const CellRef* __restrict__ small,
-                                                                     uint32_t n_small, uint32_t lv_small)
+                                                                     uint32_t n_small, uint32_t lv_small,
+                                                                     uint32_t nsteps)
 {
-    collide_entry<double>(big, n_big, lv_big, small, n_small, lv_small);
+    collide_entry<double>(big, n_big, lv_big, small, n_small, lv_small, nsteps);
 }
 
 #ifdef TRMC_PHASE_TIMING

@@ -401,12 +401,12 @@ __global__ __launch_bounds__(256) void k_moments(const CellRef* __restrict__ wor
 }
 
 // End of a step: advance the step counter, flip the slab buffer.
-__global__ void k_advance(InstDev* const* __restrict__ insts, uint32_t n_inst)
+__global__ void k_advance(InstDev* const* __restrict__ insts, uint32_t n_inst, uint32_t inc)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_inst) return;
     InstDev* I = insts[i];
-    I->step += 1u;
+    I->step += inc;  // inc > 1 only for homogeneous instances (fused steps)
     if (I->geometry == GEOM_SLAB) {
         I->cur ^= 1u;
         if (I->bc != 0u) I->n_live = I->n_next;

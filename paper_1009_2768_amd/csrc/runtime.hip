@@ -15,13 +15,13 @@
 
 namespace trmc {
 template <typename T>
-__global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
+__global__ void k_collide(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t, uint32_t);
 template <typename T>
-__global__ void k_collide_wb(const CellRef*, uint32_t, uint32_t);
+__global__ void k_collide_wb(const CellRef*, uint32_t, uint32_t, uint32_t);
 template <typename T>
 __global__ void k_inject(const CellRef*, uint32_t);
 template <typename T>
-__global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t);
+__global__ void k_collide_reuse(const CellRef*, uint32_t, uint32_t, const CellRef*, uint32_t, uint32_t, uint32_t);
 template <typename T>
 __global__ void k_hist(const CellRef*, const uint32_t*, uint32_t);
 __global__ void k_scan_tiles(const CellRef*, const uint32_t*, uint32_t);
@@ -49,7 +49,7 @@ template <typename T>
 __global__ void k_tile_zsum(const CellRef*, const uint32_t*, uint32_t);
 template <typename T>
 __global__ void k_tile_write(const CellRef*, const uint32_t*, uint32_t);
-__global__ void k_advance(InstDev* const*, uint32_t);
+__global__ void k_advance(InstDev* const*, uint32_t, uint32_t);
 }  // namespace trmc
 
 using namespace trmc;
@@ -193,6 +193,10 @@ struct trmc_ctx {
     bool use_graph = false;
     bool graph_dirty = true;
     bool tables_dirty = false;  // admissions or retirements since the work lists were built
+    // several steps in one launch per collision kernel: allowed (trmc_fuse_steps)
+    // and possible (every active instance homogeneous, no cell on the tiled path)
+    bool fuse = true;
+    bool fusable = false;
     hipStream_t cap_stream = nullptr;  // stream the step is captured on
     // the tile pipeline of large homogeneous cells runs on a second stream, beside
     // the slab sort and the whole-cell kernels (they touch different cells)
@@ -312,6 +316,7 @@ int rebuild_tables(trmc_ctx* c)
         if (e != hipSuccess) return TRMC_EIO;
     }
     c->n_active = (uint32_t)ptrs.size();
+    c->fusable = c->n_active > 0 && c->n_slab[0] + c->n_slab[1] == 0 && c->n_work[0][2] + c->n_work[1][2] == 0;
     c->graph_dirty = true;
     // the host vectors die here: make the copies complete first
     return hip_status(hipStreamSynchronize(c->stream));
@@ -507,9 +512,11 @@ int launch_tiled(trmc_ctx* c, int k)
     return hip_status(hipGetLastError());
 }
 
-// The whole-cell kernels of precision k (every cell not on the tiled pipeline).
+// The whole-cell kernels of precision k (every cell not on the tiled pipeline),
+// each cell taken through nsteps steps (nsteps > 1 only when the context is
+// fusable).
 template <typename T>
-int launch_whole(trmc_ctx* c, int k)
+int launch_whole(trmc_ctx* c, int k, uint32_t nsteps = 1)
 {
     const uint32_t nb = c->n_work[k][0], ns = c->n_work[k][1];
     if (nb + ns) {
@@ -517,11 +524,11 @@ int launch_whole(trmc_ctx* c, int k)
         const size_t lds = std::max(sizeof(uint32_t) * 5 * c->lv_stride[k][0],
                                     sizeof(uint32_t) * 5 * kSmallPerBlock * c->lv_stride[k][1]);
         hipLaunchKernelGGL(k_collide<T>, dim3(nb + small_blocks), dim3(kCollideThreads), lds, c->stream,
-                           c->work[k][0], nb, c->lv_stride[k][0], c->work[k][1], ns, c->lv_stride[k][1]);
+                           c->work[k][0], nb, c->lv_stride[k][0], c->work[k][1], ns, c->lv_stride[k][1], nsteps);
     }
     if (const uint32_t nw = c->n_work[k][3]) {
         hipLaunchKernelGGL(k_collide_wb<T>, dim3(nw), dim3(kCollideThreads), sizeof(uint32_t) * 5 * c->lv_stride[k][3],
-                           c->stream, c->work[k][3], nw, c->lv_stride[k][3]);
+                           c->stream, c->work[k][3], nw, c->lv_stride[k][3], nsteps);
     }
     const uint32_t rb = c->n_work[k][4], rs = c->n_work[k][5];
     if (rb + rs) {
@@ -529,7 +536,7 @@ int launch_whole(trmc_ctx* c, int k)
         const size_t lds = std::max(sizeof(uint32_t) * 6 * c->lv_stride[k][4],
                                     sizeof(uint32_t) * 6 * kSmallPerBlock * c->lv_stride[k][5]);
         hipLaunchKernelGGL(k_collide_reuse<T>, dim3(rb + small_blocks), dim3(kCollideThreads), lds, c->stream,
-                           c->work[k][4], rb, c->lv_stride[k][4], c->work[k][5], rs, c->lv_stride[k][5]);
+                           c->work[k][4], rb, c->lv_stride[k][4], c->work[k][5], rs, c->lv_stride[k][5], nsteps);
     }
     return hip_status(hipGetLastError());
 }
@@ -692,9 +699,23 @@ int enqueue_step(trmc_ctx* c, hipStream_t st)
     if (fork && hipStreamWaitEvent(st, c->ev_join, 0) != hipSuccess && !rc) rc = TRMC_EIO;
     if (!rc && c->n_active)
         hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, st, c->inst_ptrs,
-                           c->n_active);
+                           c->n_active, 1u);
     if (!rc && hipGetLastError() != hipSuccess) rc = TRMC_EIO;
     c->stream = keep;
+    return rc;
+}
+
+// n steps of a fusable context: one launch per collision kernel takes every
+// cell through the n steps (a cell's step depends on its own previous step
+// only), then the step counters advance by n.
+int enqueue_fused(trmc_ctx* c, uint32_t n)
+{
+    int rc = 0;
+    for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_whole<float>(c, 0, n) : launch_whole<double>(c, 1, n);
+    if (!rc)
+        hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, c->stream, c->inst_ptrs,
+                           c->n_active, n);
+    if (!rc && hipGetLastError() != hipSuccess) rc = TRMC_EIO;
     return rc;
 }
 
@@ -760,6 +781,13 @@ int trmc_step(trmc_ctx* c, uint32_t n_steps)
         if (rc) return c->sticky = rc;
         c->tables_dirty = false;
     }
+    if (c->fuse && c->fusable && n_steps > 1) {
+        const int rc = enqueue_fused(c, n_steps);
+        if (rc) return c->sticky = rc;
+        for (auto& s : c->slots)
+            if (s.active) s.steps += n_steps;
+        return 0;
+    }
     if (const int rc = ensure_side(c)) return c->sticky = rc;
     if (c->use_graph && c->graph_dirty) {
         const int rc = capture_step(c);
@@ -791,6 +819,14 @@ int trmc_get_schedule(const trmc_ctx* c, uint32_t* paths, uint32_t n_buckets)
 {
     if (!c || (n_buckets && !paths) || n_buckets > TRMC_SCHED_BUCKETS) return TRMC_EINVAL;
     for (uint32_t b = 0; b < n_buckets; ++b) paths[b] = c->sched[b];
+    return 0;
+}
+
+int trmc_fuse_steps(trmc_ctx* c, int on)
+{
+    if (!c) return TRMC_EINVAL;
+    if (c->sticky) return c->sticky;
+    c->fuse = on != 0;
     return 0;
 }
 
