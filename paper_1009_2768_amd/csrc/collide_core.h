@@ -659,7 +659,10 @@ __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, 
                                             uint32_t kept_end, uint32_t leaf_end, uint32_t r_done, bool pool_all,
                                             double mx, double my, double mz, uint32_t tid, double (&sums)[6])
 {
-    constexpr int U = 4;
+#ifndef TRMC_GATHER_UNROLL
+#define TRMC_GATHER_UNROLL 4
+#endif
+    constexpr int U = TRMC_GATHER_UNROLL;  // slots per thread per batch
     const uint32_t P = n - N0;
     for (uint32_t s0 = s_begin + tid; s0 < s_end; s0 += NT * U) {
         uint32_t ro[U];

@@ -65,7 +65,13 @@ __device__ unsigned long long g_maxcell[12];
     } while (0)
 #endif
 
-constexpr int kUnroll = 2;
+#ifndef TRMC_SLOT_UNROLL
+#define TRMC_SLOT_UNROLL 2
+#endif
+#ifndef TRMC_WRITE_UNROLL
+#define TRMC_WRITE_UNROLL 4
+#endif
+constexpr int kUnroll = TRMC_SLOT_UNROLL;  // slots per thread per batch in the moment and normal passes
 
 // One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
 // it once per step, and inlined into their step loops the compiler keeps
@@ -451,7 +457,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         const double a = uni(sh.a_th);
         const double u0 = uni(sh.ur[0]), u1 = uni(sh.ur[1]), u2 = uni(sh.ur[2]);
         const double z0 = uni(sh.zbar[0]), z1 = uni(sh.zbar[1]), z2 = uni(sh.zbar[2]);
-        constexpr int kWU = 2;
+        constexpr int kWU = TRMC_WRITE_UNROLL;
         // the roles of a batch, then the finals of its leaf slots (final r of
         // leaf r); thermalized slots draw their normals again
         for (uint32_t s0 = tid; s0 < n; s0 += G * kWU) {
