@@ -262,7 +262,8 @@ def tree_shape_truncation(T, n_inst, seed, steps=5):
     """Tree-shape truncation (Sec. 4.4) beside the plain step on one workload:
     n_inst homogeneous hard-sphere instances of 50,000 bi-Maxwellian particles
     (the paper's homogeneous test size), eps = 0.2, fixed depth 24, FP32 with
-    FP64 sums.  Plain, def:2 with m_max 2 and def:3 with m_max 3, same keys."""
+    FP64 sums.  Plain, def:2 with m_max 2 and def:3 with m_max 3, same keys, all
+    on the workgroup-per-cell path (the only path of the truncated step)."""
     import numpy as np
     import torch
 
@@ -278,6 +279,7 @@ def tree_shape_truncation(T, n_inst, seed, steps=5):
                                     precision=T.FP32_MIXED, uid=5000 + i, seed=seed, wb=wb, wb_mmax=mmax))
             parts.append({k: torch.from_numpy(v.astype(np.float32)).cuda() for k, v in zip(("vx", "vy", "vz"), a)})
         ctx = T.Context(insts, parts)
+        ctx.set_schedule([T.PATH_GROUP] * T.SCHED_BUCKETS)
         ctx.use_graph(True)
         ctx.step(1)
         ctx.sync()

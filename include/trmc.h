@@ -159,9 +159,9 @@ int trmc_init(trmc_ctx** out, const trmc_desc* descs, uint32_t n_inst, const trm
  * asynchronously on the context's stream.  When every active instance is
  * space-homogeneous and no cell is on the TILED path, and step fusion is on
  * (trmc_fuse_steps, the default), n_steps > 1 runs as one launch per collision
- * kernel in which each cell goes through the n_steps steps back to back (a
- * homogeneous cell's step reads nothing but its own previous step); the results
- * are identical to n_steps single steps. */
+ * kernel for every 32 steps, in which each cell goes through those steps back to
+ * back (a homogeneous cell's step reads nothing but its own previous step); the
+ * results are identical to n_steps single steps. */
 int trmc_step(trmc_ctx* ctx, uint32_t n_steps);
 
 /* Moments and counters of instance `slot`, one entry per cell (cap >= n_cells).

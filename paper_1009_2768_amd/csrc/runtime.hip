@@ -706,16 +706,23 @@ int enqueue_step(trmc_ctx* c, hipStream_t st)
 }
 
 // n steps of a fusable context: one launch per collision kernel takes every
-// cell through the n steps (a cell's step depends on its own previous step
-// only), then the step counters advance by n.
+// cell through up to kFuseMax steps (a cell's step depends on its own previous
+// step only), then the step counters advance by as many; longer calls are cut
+// into such chunks so that no single launch runs for long.
+constexpr uint32_t kFuseMax = 32;
+
 int enqueue_fused(trmc_ctx* c, uint32_t n)
 {
     int rc = 0;
-    for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_whole<float>(c, 0, n) : launch_whole<double>(c, 1, n);
-    if (!rc)
-        hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, c->stream, c->inst_ptrs,
-                           c->n_active, n);
-    if (!rc && hipGetLastError() != hipSuccess) rc = TRMC_EIO;
+    for (uint32_t done = 0; done < n && !rc;) {
+        const uint32_t m = std::min(kFuseMax, n - done);
+        for (int k = 0; k < 2 && !rc; ++k) rc = k == 0 ? launch_whole<float>(c, 0, m) : launch_whole<double>(c, 1, m);
+        if (!rc)
+            hipLaunchKernelGGL(k_advance, dim3((c->n_active + 255) / 256), dim3(256), 0, c->stream, c->inst_ptrs,
+                               c->n_active, m);
+        if (!rc && hipGetLastError() != hipSuccess) rc = TRMC_EIO;
+        done += m;
+    }
     return rc;
 }
 

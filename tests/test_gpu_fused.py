@@ -116,11 +116,17 @@ def test_fused_steps_equal_single_steps(trmc, prec):
     # the counters really moved on, and some cell redid or extended an attempt
     assert fused.read(0)["step"] == 5
     assert max(attempts) > 1
-    # a second fused call continues from the step index the first left
+    # a second fused call continues from the step index the first left; a call
+    # longer than one launch's 32 steps is cut into launches
     fused.step(3)
     single.step(2)
     single.step(1)
     assert_same(T, fused, single, len(insts), "8 steps")
+    fused.step(40)
+    for _ in range(40):
+        single.step(1)
+    assert_same(T, fused, single, len(insts), "48 steps")
+    assert fused.read(0)["step"] == 48
     fused.close()
     single.close()
 
