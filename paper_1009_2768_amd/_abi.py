@@ -77,6 +77,11 @@ def load():
     path = lib_path()
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it first (python -m paper_1009_2768_amd.build)")
+    # torch ships its own HIP runtime under the same soname as ROCm's: load it
+    # first, so that the library binds to the runtime that owns torch's device
+    # memory and streams (loaded the other way round, two runtimes coexist and
+    # the library's copies of torch tensors fail)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp, u32, sz, i = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_int

@@ -239,6 +239,7 @@ struct CellShared {
     double mean[3];
     double Sn, q, g, ur[3], a_th, zbar[3], E1, kept0;
     double rs[4];  // tree-shape truncation: split remainder's sums of v - mean (3) and |v - mean|^2
+    double wbz[9]; // tree-shape truncation: the dropped finals' sums (WbAcc, group totals)
     uint32_t me, split_rem, R0, N0, borrowed, n_th, folds, m, attempts, decision, overflow, wb_th;
     unsigned long long ncoll, work;
     uint32_t dummies, viol;
@@ -710,15 +711,31 @@ __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, 
 #endif
 constexpr int kBU = TRMC_BOTTOM_UP_BATCH;  // collisions per thread per batch in bottom_up
 
+// Tree-shape truncation: the finals longer than m_max, summed where they are
+// made.  z: the normals of their slots (sum of the 3 components, sum of |z|^2);
+// d: their values less the cell mean (3 sums, sum of |v - mean|^2); cnt: count.
+struct WbAcc {
+    double z[4], d[4], cnt;
+};
+
 template <typename T, int G, bool FromSlots, bool WB = false, bool REUSE = false>
 __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const T> vx, gptr<const T> vy,
                                           gptr<const T> vz,
                                           const Levels& L, const CellShared& sh, const CellMem<T>& M,
                                           unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
                                           uint32_t& dummies, uint32_t& viol, double& sfin, uint32_t wbk = 0,
-                                          const uint32_t* coff = nullptr, uint32_t r0prev = 0)
+                                          const uint32_t* coff = nullptr, uint32_t r0prev = 0,
+                                          WbAcc* wba = nullptr, T wbmax = T(0))
 {
     const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
+    // tree-shape truncation: a dropped final's slot is the permutation of its
+    // leaf's role index, where its Maxwellian normals are drawn
+    [[maybe_unused]] uint4 pk{};
+    [[maybe_unused]] uint32_t pbits = 0;
+    if constexpr (WB) {
+        pk = draw(key, 0, TAG_PERM, 0);
+        pbits = perm_bits(n);
+    }
     unsigned long long above = ncoll;  // collisions of deeper levels precede level l's
     uint32_t fp = REUSE ? r0prev : 0u; // finals of shallower levels (and of earlier attempts)
     // leaves of this attempt: ranks from r0prev on (reuse) or from 0
@@ -796,6 +813,23 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                         st4(M.fin + r, out[e].x, out[e].y, out[e].z, len[k]);
                         const double d = (double)out[e].x - mx;
                         sfin += d * d;
+                        if constexpr (WB) {
+                            if (len[k] > wbmax) {
+                                const uint32_t sl = perm_forward(leaf_role(r, N0, P), n, pbits, pk);
+                                const Vec3<T> z = Draws<T>::normals(key, sl);  // keyed by the slot
+                                const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
+                                wba->z[0] += zx;
+                                wba->z[1] += zy;
+                                wba->z[2] += zz;
+                                wba->z[3] += zx * zx + zy * zy + zz * zz;
+                                const double dy = (double)out[e].y - sh.mean[1], dz = (double)out[e].z - sh.mean[2];
+                                wba->d[0] += d;
+                                wba->d[1] += dy;
+                                wba->d[2] += dz;
+                                wba->d[3] += d * d + dy * dy + dz * dz;
+                                wba->cnt += 1.0;
+                            }
+                        }
                     }
                 }
             }

@@ -296,8 +296,16 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
 
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
+        [[maybe_unused]] WbAcc wba{};
         bottom_up<T, G, false, WB, REUSE>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol,
-                                          sfin, WB ? uni(I->wb) : 0u, coff, r0prev);
+                                          sfin, WB ? uni(I->wb) : 0u, coff, r0prev, &wba,
+                                          WB ? (T)uni(I->wb_mmax) : T(0));
+        if constexpr (WB) {
+            double v[9] = {wba.z[0], wba.z[1], wba.z[2], wba.z[3], wba.d[0], wba.d[1], wba.d[2], wba.d[3], wba.cnt};
+            gsum<G, 9>(v, gl.red);
+            if (tid == 0)
+                for (int q = 0; q < 9; ++q) sh.wbz[q] = v[q];
+        }
         TRMC_PHASE(4);
         if constexpr (REUSE) {
             sfin_acc += sfin;  // the finals of every attempt enter S
@@ -362,24 +370,11 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     if constexpr (WB) {
         // tree-shape truncation (Sec. 4.4): finals longer than m_max join the
         // remainder; their dropped values join the removed set of the rescale.
-        // Normals of every thermalized slot and the dropped finals' sums.
-        double zs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        // The collision pass summed the dropped finals and their slots' normals
+        // (sh.wbz); here the normals of the split remainder's slots.
+        double zs[4] = {0, 0, 0, 0};
         for (uint32_t s = tid; s < n; s += G) {
-            const uint32_t i = M.role[s];
-            bool th = i >= leaf_end;
-            if (i >= kept_end && i < leaf_end) {
-                const Pack4<T> f = ld4(M.fin + leaf_rank(i, N0, P));
-                if (f.w > wb_max) {
-                    th = true;
-                    const double dx = (double)f.x - mx, dy = (double)f.y - my, dz = (double)f.z - mz;
-                    zs[4] += dx;
-                    zs[5] += dy;
-                    zs[6] += dz;
-                    zs[7] += dx * dx + dy * dy + dz * dz;
-                    zs[8] += 1.0;
-                }
-            }
-            if (th) {
+            if (M.role[s] >= leaf_end) {
                 const Vec3<T> z = Draws<T>::normals(key, s);  // keyed by the slot
                 const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
                 zs[0] += zx;
@@ -388,19 +383,21 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                 zs[3] += zx * zx + zy * zy + zz * zz;
             }
         }
-        gsum<G, 9>(zs, gl.red);
+        gsum<G, 4>(zs, gl.red);
         if (tid == 0) {
-            const uint32_t n_wb = (uint32_t)zs[8];
+            for (int q = 0; q < 4; ++q) zs[q] += sh.wbz[q];
+            const double zs4 = sh.wbz[4], zs5 = sh.wbz[5], zs6 = sh.wbz[6], zs7 = sh.wbz[7];
+            const uint32_t n_wb = (uint32_t)sh.wbz[8];
             const uint32_t total = sh.n_th + n_wb;
             sh.wb_th = n_wb;
             sh.n_th = total;
             if (total >= 2) {
                 const double nt = (double)total;
-                const double d0 = (sh.rs[0] + zs[4]) / nt, d1 = (sh.rs[1] + zs[5]) / nt, d2 = (sh.rs[2] + zs[6]) / nt;
+                const double d0 = (sh.rs[0] + zs4) / nt, d1 = (sh.rs[1] + zs5) / nt, d2 = (sh.rs[2] + zs6) / nt;
                 sh.ur[0] = mx + d0;
                 sh.ur[1] = my + d1;
                 sh.ur[2] = mz + d2;
-                double E = (sh.rs[3] + zs[7]) - nt * (d0 * d0 + d1 * d1 + d2 * d2);
+                double E = (sh.rs[3] + zs7) - nt * (d0 * d0 + d1 * d1 + d2 * d2);
                 E = E > 0.0 ? E : 0.0;
                 const double zb0 = zs[0] / nt, zb1 = zs[1] / nt, zb2 = zs[2] / nt;
                 const double Z = zs[3] - nt * (zb0 * zb0 + zb1 * zb1 + zb2 * zb2);
@@ -550,8 +547,8 @@ k_collide<float>(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_bi
 
 // Cells of instances with tree-shape truncation: one workgroup per cell.
 template <typename T>
-__global__ __launch_bounds__(kCollideThreads) void k_collide_wb(const CellRef* __restrict__ work, uint32_t n_work,
-                                                                uint32_t lv_stride, uint32_t nsteps)
+__device__ __forceinline__ void collide_entry_wb(const CellRef* __restrict__ work, uint32_t n_work,
+                                                 uint32_t lv_stride, uint32_t nsteps)
 {
     for (uint32_t s = 0; s < nsteps; ++s) {
         uint32_t b = blockIdx.x;
@@ -560,8 +557,27 @@ __global__ __launch_bounds__(kCollideThreads) void k_collide_wb(const CellRef* _
         gsync<kCollideThreads>();
     }
 }
-template __global__ void k_collide_wb<float>(const CellRef*, uint32_t, uint32_t, uint32_t);
-template __global__ void k_collide_wb<double>(const CellRef*, uint32_t, uint32_t, uint32_t);
+
+#ifndef TRMC_WB_F32_WAVES_PER_EU
+#define TRMC_WB_F32_WAVES_PER_EU 3
+#endif
+template <typename T>
+__global__ void k_collide_wb(const CellRef*, uint32_t, uint32_t, uint32_t);
+
+template <>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(TRMC_WB_F32_WAVES_PER_EU, 8))) void
+k_collide_wb<float>(const CellRef* __restrict__ work, uint32_t n_work, uint32_t lv_stride, uint32_t nsteps)
+{
+    collide_entry_wb<float>(work, n_work, lv_stride, nsteps);
+}
+
+template <>
+__global__ __launch_bounds__(kCollideThreads) void k_collide_wb<double>(const CellRef* __restrict__ work,
+                                                                        uint32_t n_work, uint32_t lv_stride,
+                                                                        uint32_t nsteps)
+{
+    collide_entry_wb<double>(work, n_work, lv_stride, nsteps);
+}
 
 // Cells of instances with the adaptive depth that keeps rejected attempts, on
 // the same two paths as k_collide (dynamic LDS per group: level arrays, then

@@ -202,6 +202,30 @@ __device__ __forceinline__ uint32_t perm_inverse(uint32_t s, uint32_t n, uint32_
     return y;
 }
 
+// The rounds in forward order: perm_forward(i) is the slot of role index i
+// (perm_inverse(perm_forward(i)) == i; cycle walking keeps the pair inverse).
+__device__ __forceinline__ uint32_t feistel_enc(uint32_t y, uint32_t b, uint4 k)
+{
+    const uint32_t lo = b >> 1, hi = b - lo;
+    const uint32_t mlo = (1u << lo) - 1u, mhi = (hi >= 32u) ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+    uint32_t H = y >> lo, W = y & mlo;
+    const uint32_t kk[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+    for (int i = 0; i <= 5; ++i) {
+        const uint32_t rk = kk[i & 3] ^ ((uint32_t)i * 0x9E3779B9u);
+        if ((i & 1) == 0) H ^= mix24(W ^ rk) & mhi;
+        else W ^= mix24(H ^ rk) & mlo;
+    }
+    return (H << lo) | W;
+}
+
+__device__ __forceinline__ uint32_t perm_forward(uint32_t i, uint32_t n, uint32_t b, uint4 k)
+{
+    uint32_t y = feistel_enc(i, b, k);
+    while (y >= n) y = feistel_enc(y, b, k);
+    return y;
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic block reductions (fixed butterfly inside a wave, then waves in
 // order).  `red` holds kCollideThreads/64 * K doubles of LDS.
