@@ -461,7 +461,9 @@ def main():
     algo_bytes = 6 * sz * total  # one read and one write of (vx, vy, vz) per particle-step
     achieved = algo_bytes / (avg_ms * 1e-3) / 1e9  # per step; a fused launch is `steps` steps
     kernel = "k_collide<float>" if prec == T.FP32_MIXED else "k_collide<double>"
-    tiled = any(table[T.size_bucket(i)] in (0, 3) for i in ctx.instances)
+    # a cell on the tile pipeline: TILED, or the library default from 2^16 particles on
+    tiled = any(table[T.size_bucket(i)] == 3 or (table[T.size_bucket(i)] == 0 and T.size_bucket(i) >= 16)
+                for i in ctx.instances)
     fuse = fuse and not tiled  # a cell on the tile pipeline keeps one launch sequence per step
     per_launch = args.steps if fuse else 1
     traffic = None if tiled else stored_traffic(kernel, table, per_launch)

@@ -241,8 +241,11 @@ int rebuild_tables(trmc_ctx* c)
         uint32_t bucket = 0;
         while (bucket + 1 < TRMC_SCHED_BUCKETS && per >= (double)(2ull << bucket)) ++bucket;
         uint32_t path = c->sched[bucket];
-        if (path == TRMC_PATH_DEFAULT) path = slab ? (per <= (double)kSmallCell ? TRMC_PATH_WAVE : TRMC_PATH_GROUP)
-                                                   : TRMC_PATH_TILED;
+        if (path == TRMC_PATH_DEFAULT) {
+            if (slab) path = per <= (double)kSmallCell ? TRMC_PATH_WAVE : TRMC_PATH_GROUP;
+            else if (per < (double)kSmallHomog) path = TRMC_PATH_WAVE;
+            else path = per >= (double)kTiledCell ? TRMC_PATH_TILED : TRMC_PATH_GROUP;
+        }
         const bool shallow = s.desc.m_cap <= kSmallDepth;
         int cls = 0;
         if (path == TRMC_PATH_TILED && !slab && shallow) cls = 2;

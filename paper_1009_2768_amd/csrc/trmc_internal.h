@@ -24,6 +24,11 @@ constexpr uint32_t kRoleBlock = 512;     // roles per block sum of the tiled pip
 constexpr uint32_t kCollideThreads = TRMC_COLLIDE_THREADS;  // threads per workgroup of the whole-cell kernel
 constexpr uint32_t kSmallPerBlock = kCollideThreads / 64;  // wave-per-cell groups per workgroup
 constexpr uint32_t kSmallCell = 4096;  // cells expected to hold at most this many particles use one wave
+// Default path of a homogeneous cell (measured crossovers on the batched
+// workload): one wave below kSmallHomog particles, the tile pipeline from
+// kTiledCell on, one workgroup between.
+constexpr uint32_t kSmallHomog = 1024;
+constexpr uint32_t kTiledCell = 65536;
 constexpr uint32_t kSmallDepth = 256;  // ... if their m_cap is at most this
 
 // Counters of one cell's last collision step.
