@@ -3,10 +3,12 @@ benchmark times.
 
 * Batched homogeneous, 4096 instances (48,356,870 particles): the whole batch is
   stepped in FP64 under the benchmark's schedule (wave path below 2048 particles,
-  workgroup path above) with the step replayed from the captured graph; sampled
-  instances across the size range are compared with the oracle run on the same
-  instances one by one (integers exact, velocities within 1e-12).  In FP32, the
-  benchmark's precision, every instance conserves momentum and energy to 1e-6.
+  workgroup path above), two steps in one call (one fused launch, as the
+  benchmark times its steps); sampled instances across the size range are
+  compared with the oracle run on the same instances one by one (integers
+  exact, velocities within 1e-12).  In FP32, the benchmark's precision, every
+  instance conserves momentum and energy to 1e-6 per step, stepped one launch
+  per step from the captured graph and then 20 steps in one fused launch.
 * Transition-regime tube, 10^4 cells and 10^7 particles with eps(x) from 1e-4 to
   1 (hard spheres, FP64): one step against the oracle over every cell.
 * Sod tube, 200 cells and 10^5 particles (hard spheres, eps = 1e-2): 200 steps in
@@ -114,6 +116,14 @@ def test_batched_4096_fp32_conservation_every_instance(trmc):
         assert dp.max() <= 1e-6, (int(dp.argmax()), float(dp.max()))
         assert de.max() <= 1e-6, (int(de.argmax()), float(de.max()))
         p0, a0, e0 = p1, a1, e1
+    # the benchmark's timed call: 20 steps in one fused launch (bound: 20 x the per-step one)
+    ctx.step(20)
+    ctx.sync()
+    p1, a1, e1 = sums()
+    dp = np.abs(p1 - p0).max(0) / a0
+    de = np.abs(e1 - e0) / e0
+    assert dp.max() <= 2e-5, (int(dp.argmax()), float(dp.max()))
+    assert de.max() <= 2e-5, (int(de.argmax()), float(de.max()))
     ctx.close()
 
 
