@@ -348,6 +348,35 @@ def stationary_shock(T, seed, steps=400, average_from=200):
     return out
 
 
+def tubes(T, seed, steps=20, warmup=5):
+    """The two shock-tube workloads in FP32 with FP64 cell sums, hard spheres,
+    adaptive depth, specular walls, dt = CFL 0.5: the Sod tube (200 cells, 500
+    particles per cell on average, eps 1e-2) and the transition-regime tube
+    (10^4 cells x 1000 particles on average, eps(x) log-linear from 1e-4 to 1).
+    A slab's steps are not fused (transport and sort between steps): one graph
+    replay per step, timed with HIP events on the library's stream."""
+    import torch
+
+    import workloads as W
+    out = {}
+    for name, nc, ppl, ppr, eps in (("sod_200", 200, 889, 111, 1e-2),
+                                    ("transition_1e4", 10000, 1778, 222, None)):
+        x, vx, vy, vz, w = W.sod(nc, ppl, ppr, seed=seed)
+        e = W.transition_eps(nc) if eps is None else None
+        inst = T.Instance(n_particles=len(x), geometry=T.SLAB1D, n_cells=nc, dt=W.sod_dt(1.0, nc),
+                          eps=1.0 if eps is None else eps, eps_cells=e, alpha=1.0, trunc=T.ADAPTIVE, m_init=2,
+                          m_cap=64, particle_weight=w, uid=8000 + nc, seed=seed, precision=T.FP32_MIXED)
+        ctx = T.Context([inst], [T.device_particles(vx, vy, vz, x, T.FP32_MIXED)])
+        ctx.use_graph(True)
+        wall, kernel_ms = time_steps(ctx, steps, warmup, True)
+        out[name] = {"cells": nc, "particles": len(x), "ms_per_step": wall * 1e3 / steps, "event_ms": kernel_ms,
+                     "particle_steps_per_s": len(x) * steps / wall}
+        log(f"tube {name}: {out[name]}")
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(T, args):
     """Serving run: a Poisson stream of homogeneous solves and shock tubes (N
     log-uniform in [1e3, 1e6], 50-500 steps, eps log-uniform in [1e-4, 1]) served
@@ -404,6 +433,7 @@ def main():
     ap.add_argument("--no-reuse", action="store_true",
                     help="skip the run of the workload with the adaptive depth that keeps rejected attempts")
     ap.add_argument("--no-shock", action="store_true", help="skip the stationary-shock run")
+    ap.add_argument("--no-tubes", action="store_true", help="skip the Sod and transition-regime tube runs")
     ap.add_argument("--wb-instances", type=int, default=64,
                     help="instances of the tree-shape truncation comparison (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -514,6 +544,8 @@ def main():
         log(f"batching: {line['batching']}")
     if not args.no_shock:
         line["stationary_shock"] = stationary_shock(T, args.seed)
+    if not args.no_tubes:
+        line["tubes"] = tubes(T, args.seed)
     if args.wb_instances > 0:
         line["tree_shape_truncation"] = tree_shape_truncation(T, args.wb_instances, args.seed)
     if args.serve_seconds > 0:
