@@ -78,15 +78,6 @@ __device__ __forceinline__ uint32_t slab_step(const InstDev* I, T& x, T& v, T dt
     return open ? slab_move_open<T>(x, v, dt, L, inv_dx, nc) : slab_move<T>(x, v, dt, L, inv_dx, nc);
 }
 
-// Tile size used by the sort of an instance with n_cells cells: at least 4 cells'
-// worth of counters per particle... i.e. the dense histogram costs <= 1 byte per particle.
-__host__ __device__ inline uint32_t sort_tile(uint32_t n_cells)
-{
-    uint32_t t = 4u * n_cells;
-    t = (t + 1023u) & ~1023u;
-    return t < kSortTile ? kSortTile : t;
-}
-
 // The sort kernels run every slab of a precision in one launch: flat block t is
 // tile k of slab b (tile_of over the prefix of the slabs' tile counts).
 template <typename T>
@@ -111,10 +102,24 @@ __global__ __launch_bounds__(1024) void k_hist(const CellRef* __restrict__ slabs
     const T* __restrict__ vx = reinterpret_cast<const T*>(I->vx[cur]);
     const T dt = (T)I->dt, L = (T)I->length;
     const double inv_dx = I->inv_dx;
-    for (uint64_t p = t0 + threadIdx.x; p < t1; p += blockDim.x) {
-        T xp = x[p], vp = vx[p];
-        const uint32_t c = slab_step<T>(I, xp, vp, dt, L, inv_dx, nc, open);
-        atomicAdd(&hist[c], 1u);
+    // four particles per thread per round: all loads of a round are issued before
+    // the first count
+    constexpr uint32_t kU = 4;
+    for (uint64_t p0 = t0 + threadIdx.x; p0 < t1; p0 += (uint64_t)kU * blockDim.x) {
+        T xp[kU], vp[kU];
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+            const uint64_t p = p0 + (uint64_t)u * blockDim.x;
+            xp[u] = p < t1 ? x[p] : T(0);
+            vp[u] = p < t1 ? vx[p] : T(0);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+            if (p0 + (uint64_t)u * blockDim.x < t1) {
+                const uint32_t c = slab_step<T>(I, xp[u], vp[u], dt, L, inv_dx, nc, open);
+                atomicAdd(&hist[c], 1u);
+            }
+        }
     }
     __syncthreads();
     uint32_t* out = I->hist + (uint64_t)kt * nb;
@@ -133,11 +138,25 @@ __global__ __launch_bounds__(256) void k_scan_tiles(const CellRef* __restrict__ 
     const uint32_t c = kb * blockDim.x + threadIdx.x;
     if (c >= nb) return;
     const uint32_t nt = I->n_tiles;
+    uint32_t* const col = I->hist + c;
     uint32_t acc = 0;
-    for (uint32_t t = 0; t < nt; ++t) {
-        uint32_t* h = I->hist + (uint64_t)t * nb + c;
-        const uint32_t v = *h;
-        *h = acc;
+    uint32_t t = 0;
+    // eight tiles per round: the round's loads are issued before its stores (the
+    // rows are distinct, so no store of a round meets one of its loads)
+    constexpr uint32_t kR = 8;
+    for (; t + kR <= nt; t += kR) {
+        uint32_t v[kR];
+#pragma unroll
+        for (uint32_t u = 0; u < kR; ++u) v[u] = col[(uint64_t)(t + u) * nb];
+#pragma unroll
+        for (uint32_t u = 0; u < kR; ++u) {
+            col[(uint64_t)(t + u) * nb] = acc;
+            acc += v[u];
+        }
+    }
+    for (; t < nt; ++t) {
+        const uint32_t v = col[(uint64_t)t * nb];
+        col[(uint64_t)t * nb] = acc;
         acc += v;
     }
     I->cell_off[c + 1] = acc;  // counts, scanned by k_scan_cells
@@ -211,18 +230,28 @@ __global__ __launch_bounds__(1024) void k_scatter(const CellRef* __restrict__ sl
     const double inv_dx = I->inv_dx;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64u - lane));
+    // the next chunk's particle is loaded while this chunk is ranked and written
+    T nx = T(0), nv = T(0), ny = T(0), nz = T(0);
+    if (t0 + threadIdx.x < t1) {
+        const uint64_t p = t0 + threadIdx.x;
+        nx = x[p];
+        nv = vx[p];
+        ny = vy[p];
+        nz = vz[p];
+    }
     for (uint64_t cb = t0; cb < t1; cb += blockDim.x) {
         const uint64_t p = cb + threadIdx.x;
         const bool valid = p < t1;
-        T xp = T(0), vp = T(0), wy = T(0), wz = T(0);
-        uint32_t c = 0;
-        if (valid) {
-            xp = x[p];
-            vp = vx[p];
-            wy = vy[p];
-            wz = vz[p];
-            c = slab_step<T>(I, xp, vp, dt, L, inv_dx, nc, open);
+        T xp = nx, vp = nv, wy = ny, wz = nz;
+        const uint64_t pn = p + blockDim.x;
+        if (pn < t1) {
+            nx = x[pn];
+            nv = vx[pn];
+            ny = vy[pn];
+            nz = vz[pn];
         }
+        uint32_t c = 0;
+        if (valid) c = slab_step<T>(I, xp, vp, dt, L, inv_dx, nc, open);
         // distinct cells of the wave, in lane order of first appearance
         bool pend = valid;
         uint32_t my_rank = 0, my_k = 0, k = 0;

@@ -59,13 +59,6 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t al(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
 
-uint32_t sort_tile_h(uint32_t n_cells)
-{
-    uint32_t t = 4u * n_cells;
-    t = (t + 1023u) & ~1023u;
-    return t < kSortTile ? kSortTile : t;
-}
-
 struct Layout {
     size_t inst, refs, eps, off, mstate, stats, mom, hist, bx, bvx, bvy, bvz, tpart, bsum, big, scratch, total;
     uint32_t n_tiles;
@@ -87,7 +80,7 @@ Layout layout_of(const trmc_desc& d)
     L.mom = p;     p += al(sizeof(double) * 9 * nc);
     L.n_tiles = 0;
     if (d.geometry == TRMC_SLAB1D) {
-        const uint32_t tile = sort_tile_h(nc);
+        const uint32_t tile = sort_tile(nc);
         L.n_tiles = (uint32_t)((n + tile - 1) / tile);
         L.hist = p;  p += al(sizeof(uint32_t) * (size_t)L.n_tiles * (nc + 1));
         L.bx = p;    p += al(sz * n);

@@ -14,7 +14,19 @@ enum : uint32_t { CELL_OVERFLOW = 1u, INJECT_FULL = 2u };  // context error word
 
 constexpr uint32_t kMaxDepth = 2048;     // largest m_cap accepted
 constexpr uint32_t kMaxSlabCells = 12288;  // LDS histogram of the sort
-constexpr uint32_t kSortTile = 4096;     // particles per tile of the counting sort
+constexpr uint32_t kSortTile = 4096;     // fewest particles per tile of the counting sort
+#ifndef TRMC_SORT_TILE_CELLS
+#define TRMC_SORT_TILE_CELLS 2
+#endif
+// Particles per tile of the counting sort of a slab with n_cells cells (host and
+// device): TRMC_SORT_TILE_CELLS particles per counter of the tile's dense
+// histogram, rounded up to 1024, at least kSortTile.
+__host__ __device__ inline uint32_t sort_tile(uint32_t n_cells)
+{
+    uint32_t t = TRMC_SORT_TILE_CELLS * n_cells;
+    t = (t + 1023u) & ~1023u;
+    return t < kSortTile ? kSortTile : t;
+}
 constexpr uint32_t kTile = 8192;         // slots per tile of the tiled collision pipeline
 constexpr uint32_t kBigStateBytes = 1024; // per-cell state of the tiled pipeline (before its level arrays)
 constexpr uint32_t kRoleBlock = 512;     // roles per block sum of the tiled pipeline
