@@ -168,6 +168,16 @@ int trmc_step(trmc_ctx* ctx, uint32_t n_steps);
  * Synchronises the stream. */
 int trmc_moments(trmc_ctx* ctx, uint32_t slot, trmc_cell_moments* host_out, uint32_t cap);
 
+/* As trmc_moments, without waiting: the moments and counters of `slot` are
+ * computed and written to out[0 .. n_cells) by the device, in stream order.
+ * out (cap >= n_cells entries) must be memory the device can write: device
+ * memory, or pinned host memory (hipHostMalloc).  Its contents are valid once
+ * the stream has passed this call (trmc_sync, or an event recorded after it);
+ * the slot's arrays and workspace must stay allocated until then, also when
+ * the slot is retired right after.  The serving loop reads the results of
+ * finished requests this way, so that the device never waits for the host. */
+int trmc_moments_async(trmc_ctx* ctx, uint32_t slot, trmc_cell_moments* out, uint32_t cap);
+
 /* Current device arrays of instance `slot` (a slab alternates between the
  * caller's arrays and a workspace copy; the pointers change after every step). */
 int trmc_state(trmc_ctx* ctx, uint32_t slot, trmc_particles* out);

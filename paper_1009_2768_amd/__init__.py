@@ -23,7 +23,8 @@ from ._abi import (ADAPTIVE, ADAPTIVE_REUSE, FIXED, FP32_MIXED, FP64, HOMOG, NAT
 __all__ = ["Instance", "Context", "HOMOG", "SLAB1D", "FP64", "FP32_MIXED", "NATURAL", "FIXED", "ADAPTIVE",
            "ADAPTIVE_REUSE",
            "PATH_DEFAULT", "PATH_GROUP", "PATH_WAVE", "PATH_TILED", "SCHED_BUCKETS", "WB_OFF", "WB_MIN",
-           "WB_MEAN", "BC_SPECULAR", "BC_INFLOW", "TrmcError", "load", "size_bucket"]
+           "WB_MEAN", "BC_SPECULAR", "BC_INFLOW", "TrmcError", "load", "size_bucket", "moments_record_bytes",
+           "unpack_moments"]
 
 load = _abi.load
 
@@ -120,6 +121,19 @@ def _particles(t: dict) -> _abi.Particles:
     p.x = t["x"].data_ptr() if t.get("x") is not None else None
     p.vx, p.vy, p.vz = t["vx"].data_ptr(), t["vy"].data_ptr(), t["vz"].data_ptr()
     return p
+
+
+def moments_record_bytes(n_cells: int) -> int:
+    """Bytes of the records of n_cells cells written by Context.moments_async."""
+    return n_cells * ctypes.sizeof(_abi.CellMoments)
+
+
+def unpack_moments(buf, n_cells: int) -> dict:
+    """The dict of Context.moments from a host uint8 tensor (or array) filled by
+    Context.moments_async."""
+    raw = buf.numpy() if hasattr(buf, "numpy") else np.asarray(buf)
+    rec = raw[: moments_record_bytes(n_cells)].view(np.dtype(_abi.CellMoments))
+    return {k: np.array(rec[k]) for k in rec.dtype.names}
 
 
 class Context:
@@ -234,6 +248,15 @@ class Context:
         check(self._lib.trmc_moments(self._ctx, slot, out, nc), "trmc_moments")
         names = [f[0] for f in _abi.CellMoments._fields_]
         return {k: np.array([getattr(out[c], k) for c in range(nc)]) for k in names}
+
+    def moments_async(self, slot: int, out) -> None:
+        """Enqueue the moments of `slot` into `out`, a pinned host (or device) uint8
+        tensor of at least n_cells records (moments_record_bytes); the contents are
+        valid once the context's stream has passed this call.  unpack_moments
+        turns them into the dict of moments()."""
+        cap = (out.numel() * out.element_size()) // ctypes.sizeof(_abi.CellMoments)
+        check(self._lib.trmc_moments_async(self._ctx, slot, ctypes.c_void_p(out.data_ptr()), cap),
+              "trmc_moments_async")
 
     def read(self, slot: int):
         inst = self.instance(slot)

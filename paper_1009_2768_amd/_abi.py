@@ -19,7 +19,7 @@ EXPORTS = [
     "trmc_abi_version", "trmc_strerror", "trmc_workspace_size", "trmc_ctx_workspace_size", "trmc_init",
     "trmc_step", "trmc_moments", "trmc_state", "trmc_read", "trmc_admit", "trmc_retire", "trmc_sync",
     "trmc_destroy", "trmc_set_schedule", "trmc_get_schedule", "trmc_use_graph", "trmc_count",
-    "trmc_fuse_steps",
+    "trmc_fuse_steps", "trmc_moments_async",
 ]
 
 SCHED_BUCKETS = 32
@@ -119,6 +119,8 @@ def load():
     L.trmc_use_graph.restype = i
     L.trmc_fuse_steps.argtypes = [vp, i]
     L.trmc_fuse_steps.restype = i
+    L.trmc_moments_async.argtypes = [vp, u32, vp, u32]
+    L.trmc_moments_async.restype = i
     L.trmc_count.argtypes = [vp, u32, P(ctypes.c_uint64)]
     L.trmc_count.restype = i
     _lib = L

@@ -12,6 +12,7 @@
 // The result is the stable order: by cell, then by previous position.
 #include <hip/hip_runtime.h>
 
+#include "../../include/trmc.h"
 #include "trmc_device.h"
 #include "trmc_internal.h"
 
@@ -380,9 +381,12 @@ __global__ __launch_bounds__(256) void k_inject(const CellRef* __restrict__ slab
     if (threadIdx.x == 0) I->n_live = n + kl + kr;
 }
 
-// Per-cell moments (FP64): rho, u, T, P_xx, P_yy, P_zz, M4 per unit mass.
+// Per-cell moments (FP64): rho, u, T, P_xx, P_yy, P_zz, M4 per unit mass.  With
+// out, the cell's full record (moments, counters of the last step, adaptive
+// depth) is also written to out[cell], which may be pinned host memory.
 template <typename T>
-__global__ __launch_bounds__(256) void k_moments(const CellRef* __restrict__ work, uint32_t n_work)
+__global__ __launch_bounds__(256) void k_moments(const CellRef* __restrict__ work, uint32_t n_work,
+                                                 trmc_cell_moments* __restrict__ out)
 {
     __shared__ double red[4 * 8];
     const uint32_t wi = blockIdx.x;
@@ -426,6 +430,38 @@ __global__ __launch_bounds__(256) void k_moments(const CellRef* __restrict__ wor
         o[6] = p[1] * inv;
         o[7] = p[2] * inv;
         o[8] = p[3] * inv;
+        if (out) {
+            const CellStats& st = I->stats[cell];
+            trmc_cell_moments r;
+            r.n = n;
+            r.m_state = I->m_state[cell];
+            r.rho = o[0];
+            r.ux = o[1];
+            r.uy = o[2];
+            r.uz = o[3];
+            r.T = o[4];
+            r.Pxx = o[5];
+            r.Pyy = o[6];
+            r.Pzz = o[7];
+            r.M4 = o[8];
+            r.collisions = st.collisions;
+            r.dummies = st.dummies;
+            r.violations = st.violations;
+            r.work_collisions = st.work_collisions;
+            r.thermalized = st.n_th;
+            r.borrowed = st.borrowed;
+            r.m_eff = st.m_eff;
+            r.m_used = st.m_used;
+            r.attempts = st.attempts;
+            r.N0 = st.N0;
+            r.R0 = st.R0;
+            r.status = st.status;
+            r.wb_thermalized = st.wb_th;
+            r.reserved = 0u;
+            r.q = st.q;
+            r.g = st.g;
+            out[cell] = r;
+        }
     }
 }
 
@@ -446,9 +482,9 @@ template __global__ void k_hist<float>(const CellRef*, const uint32_t*, uint32_t
 template __global__ void k_hist<double>(const CellRef*, const uint32_t*, uint32_t);
 template __global__ void k_scatter<float>(const CellRef*, const uint32_t*, uint32_t);
 template __global__ void k_scatter<double>(const CellRef*, const uint32_t*, uint32_t);
-template __global__ void k_moments<float>(const CellRef*, uint32_t);
+template __global__ void k_moments<float>(const CellRef*, uint32_t, trmc_cell_moments*);
 template __global__ void k_inject<float>(const CellRef*, uint32_t);
 template __global__ void k_inject<double>(const CellRef*, uint32_t);
-template __global__ void k_moments<double>(const CellRef*, uint32_t);
+template __global__ void k_moments<double>(const CellRef*, uint32_t, trmc_cell_moments*);
 
 }  // namespace trmc

@@ -29,7 +29,7 @@ __global__ void k_scan_cells(const CellRef*);
 template <typename T>
 __global__ void k_scatter(const CellRef*, const uint32_t*, uint32_t);
 template <typename T>
-__global__ void k_moments(const CellRef*, uint32_t);
+__global__ void k_moments(const CellRef*, uint32_t, trmc_cell_moments*);
 struct CellLists {
     uint32_t* list;
     uint32_t* count;
@@ -195,6 +195,15 @@ struct trmc_ctx {
     // the slab sort and the whole-cell kernels (they touch different cells)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // uploads (descriptors at admission, work lists at rebuild) go through a ring
+    // of pinned host buffers, each reused only after the event of its last
+    // copies, so no upload waits for the stream to drain
+    static constexpr int kStage = 8;
+    unsigned char* stage[kStage] = {};
+    size_t stage_cap[kStage] = {};
+    hipEvent_t stage_ev[kStage] = {};
+    bool stage_used[kStage] = {};
+    int stage_next = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
@@ -211,6 +220,55 @@ size_t ctx_bytes(uint32_t max_inst, uint32_t max_cells)
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? 0 : TRMC_EIO; }
+
+// Host data to upload: a byte blob and the (destination, offset, size) of each copy.
+struct Uploads {
+    std::vector<unsigned char> blob;
+    struct Item {
+        void* dst;
+        size_t off, bytes;
+    };
+    std::vector<Item> items;
+    void add(void* dst, const void* src, size_t bytes)
+    {
+        if (!bytes) return;
+        const size_t off = (blob.size() + 15) & ~size_t(15);
+        blob.resize(off + bytes);
+        std::memcpy(blob.data() + off, src, bytes);
+        items.push_back({dst, off, bytes});
+    }
+};
+
+// Copy the uploads to the device on the context's stream through the next
+// pinned staging buffer of the ring; returns without waiting for the copies.
+int stage_uploads(trmc_ctx* c, const Uploads& u)
+{
+    if (u.items.empty()) return 0;
+    const int i = c->stage_next;
+    c->stage_next = (i + 1) % trmc_ctx::kStage;
+    if (c->stage_used[i] && hipEventSynchronize(c->stage_ev[i]) != hipSuccess) return TRMC_EIO;
+    if (c->stage_cap[i] < u.blob.size()) {
+        if (c->stage[i]) (void)hipHostFree(c->stage[i]);
+        c->stage[i] = nullptr;
+        c->stage_cap[i] = 0;
+        const size_t want = std::max(u.blob.size(), std::max<size_t>(size_t(1) << 16, 2 * c->stage_cap[i]));
+        void* p = nullptr;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return TRMC_EIO;
+        c->stage[i] = static_cast<unsigned char*>(p);
+        c->stage_cap[i] = want;
+    }
+    if (!c->stage_ev[i] && hipEventCreateWithFlags(&c->stage_ev[i], hipEventDisableTiming) != hipSuccess) {
+        c->stage_ev[i] = nullptr;
+        return TRMC_EIO;
+    }
+    std::memcpy(c->stage[i], u.blob.data(), u.blob.size());
+    for (const auto& it : u.items)
+        if (hipMemcpyAsync(it.dst, c->stage[i] + it.off, it.bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return TRMC_EIO;
+    if (hipEventRecord(c->stage_ev[i], c->stream) != hipSuccess) return TRMC_EIO;
+    c->stage_used[i] = true;
+    return 0;
+}
 
 // Rebuild the device work lists and the instance list.  The path of a cell comes
 // from the schedule bucket of its expected size; WAVE and TILED need m_cap <=
@@ -248,6 +306,7 @@ int rebuild_tables(trmc_ctx* c)
         for (uint32_t cc = 0; cc < nc; ++cc) order[k][cls].push_back({per, CellRef{s.dev, cc, 0}});
         stride[k][cls] = std::max(stride[k][cls], s.desc.m_cap + 2u);
     }
+    Uploads up;
     std::vector<CellRef> w;
     std::vector<uint32_t> prefix;
     for (int k = 0; k < 2; ++k) {
@@ -256,22 +315,14 @@ int rebuild_tables(trmc_ctx* c)
             std::stable_sort(o.begin(), o.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
             w.clear();
             for (auto& e : o) w.push_back(e.second);
-            if (!w.empty()) {
-                hipError_t e = hipMemcpyAsync(c->work[k][cls], w.data(), sizeof(CellRef) * w.size(),
-                                              hipMemcpyHostToDevice, c->stream);
-                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // w is reused
-                if (e != hipSuccess) return TRMC_EIO;
-            }
+            up.add(c->work[k][cls], w.data(), sizeof(CellRef) * w.size());
             c->n_work[k][cls] = (uint32_t)w.size();
             c->lv_stride[k][cls] = stride[k][cls];
             if (cls == 2) {
                 prefix.assign(1, 0u);
                 for (auto& e : o) prefix.push_back(prefix.back() + (uint32_t)((e.first + kTile - 1) / kTile));
                 c->n_tiles[k] = prefix.back();
-                hipError_t e = hipMemcpyAsync(c->tile_prefix[k], prefix.data(), sizeof(uint32_t) * prefix.size(),
-                                              hipMemcpyHostToDevice, c->stream);
-                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-                if (e != hipSuccess) return TRMC_EIO;
+                up.add(c->tile_prefix[k], prefix.data(), sizeof(uint32_t) * prefix.size());
             }
         }
     }
@@ -296,26 +347,15 @@ int rebuild_tables(trmc_ctx* c)
         c->slab_tiles[k] = tpre[k].back();
         c->slab_cblk[k] = cpre[k].back();
         if (sref[k].empty()) continue;
-        hipError_t e = hipMemcpyAsync(c->slab_refs[k], sref[k].data(), sizeof(CellRef) * sref[k].size(),
-                                      hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->slab_tpre[k], tpre[k].data(), sizeof(uint32_t) * tpre[k].size(),
-                               hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->slab_cpre[k], cpre[k].data(), sizeof(uint32_t) * cpre[k].size(),
-                               hipMemcpyHostToDevice, c->stream);
-        if (e != hipSuccess) return TRMC_EIO;
+        up.add(c->slab_refs[k], sref[k].data(), sizeof(CellRef) * sref[k].size());
+        up.add(c->slab_tpre[k], tpre[k].data(), sizeof(uint32_t) * tpre[k].size());
+        up.add(c->slab_cpre[k], cpre[k].data(), sizeof(uint32_t) * cpre[k].size());
     }
-    if (!ptrs.empty()) {
-        hipError_t e = hipMemcpyAsync(c->inst_ptrs, ptrs.data(), sizeof(InstDev*) * ptrs.size(),
-                                      hipMemcpyHostToDevice, c->stream);
-        if (e != hipSuccess) return TRMC_EIO;
-    }
+    up.add(c->inst_ptrs, ptrs.data(), sizeof(InstDev*) * ptrs.size());
     c->n_active = (uint32_t)ptrs.size();
     c->fusable = c->n_active > 0 && c->n_slab[0] + c->n_slab[1] == 0 && c->n_work[0][2] + c->n_work[1][2] == 0;
     c->graph_dirty = true;
-    // the host vectors die here: make the copies complete first
-    return hip_status(hipStreamSynchronize(c->stream));
+    return stage_uploads(c, up);  // stream-ordered before every later launch
 }
 
 // Reservoir constants of an open slab (the same closed forms as the CPU check,
@@ -434,19 +474,14 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     }
     off[nc] = h.n_live;  // homogeneous: one cell [0, n); slab: set by the sort
     off[nc + 1] = h.n_live;
-    hipError_t e = hipSuccess;
-    e = e == hipSuccess ? hipMemcpyAsync(ws + L.inst, &h, sizeof(InstDev), hipMemcpyHostToDevice, c->stream) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(ws + L.refs, refs.data(), sizeof(CellRef) * nc, hipMemcpyHostToDevice,
-                                         c->stream) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(ws + L.eps, eps.data(), sizeof(double) * nc, hipMemcpyHostToDevice,
-                                         c->stream) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(ws + L.off, off.data(), sizeof(uint32_t) * (nc + 2),
-                                         hipMemcpyHostToDevice, c->stream) : e;
-    e = e == hipSuccess ? hipMemcpyAsync(ws + L.mstate, ms.data(), sizeof(uint32_t) * nc, hipMemcpyHostToDevice,
-                                         c->stream) : e;
-    e = e == hipSuccess ? hipMemsetAsync(ws + L.stats, 0, sizeof(CellStats) * nc, c->stream) : e;
-    e = e == hipSuccess ? hipStreamSynchronize(c->stream) : e;
-    if (e != hipSuccess) {
+    Uploads up;
+    up.add(ws + L.inst, &h, sizeof(InstDev));
+    up.add(ws + L.refs, refs.data(), sizeof(CellRef) * nc);
+    up.add(ws + L.eps, eps.data(), sizeof(double) * nc);
+    up.add(ws + L.off, off.data(), sizeof(uint32_t) * (nc + 2));
+    up.add(ws + L.mstate, ms.data(), sizeof(uint32_t) * nc);
+    hipError_t e = hipMemsetAsync(ws + L.stats, 0, sizeof(CellStats) * nc, c->stream);
+    if (e != hipSuccess || stage_uploads(c, up) != 0) {
         s.active = false;
         return TRMC_EIO;
     }
@@ -881,9 +916,9 @@ int trmc_moments(trmc_ctx* c, uint32_t slot, trmc_cell_moments* host_out, uint32
     if (cap < nc) return TRMC_EINVAL;
     const CellRef* refs = reinterpret_cast<const CellRef*>(s.ws + s.lay.refs);
     if (s.host.precision == PREC_FP64)
-        hipLaunchKernelGGL(k_moments<double>, dim3(nc), dim3(256), 0, c->stream, refs, nc);
+        hipLaunchKernelGGL(k_moments<double>, dim3(nc), dim3(256), 0, c->stream, refs, nc, nullptr);
     else
-        hipLaunchKernelGGL(k_moments<float>, dim3(nc), dim3(256), 0, c->stream, refs, nc);
+        hipLaunchKernelGGL(k_moments<float>, dim3(nc), dim3(256), 0, c->stream, refs, nc, nullptr);
     if (hipGetLastError() != hipSuccess) return c->sticky = TRMC_EIO;
     std::vector<double> mom(9ull * nc);
     std::vector<CellStats> st(nc);
@@ -928,6 +963,21 @@ int trmc_moments(trmc_ctx* c, uint32_t slot, trmc_cell_moments* host_out, uint32
         o.g = st[i].g;
     }
     return rc;
+}
+
+int trmc_moments_async(trmc_ctx* c, uint32_t slot, trmc_cell_moments* out, uint32_t cap)
+{
+    if (!c || !out || slot >= c->slots.size() || !c->slots[slot].active) return TRMC_EINVAL;
+    if (c->sticky) return c->sticky;
+    Slot& s = c->slots[slot];
+    const uint32_t nc = s.host.n_cells;
+    if (cap < nc) return TRMC_EINVAL;
+    const CellRef* refs = reinterpret_cast<const CellRef*>(s.ws + s.lay.refs);
+    if (s.host.precision == PREC_FP64)
+        hipLaunchKernelGGL(k_moments<double>, dim3(nc), dim3(256), 0, c->stream, refs, nc, out);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3(nc), dim3(256), 0, c->stream, refs, nc, out);
+    return hipGetLastError() == hipSuccess ? 0 : (c->sticky = TRMC_EIO);
 }
 
 int trmc_read(trmc_ctx* c, uint32_t slot, void* x, void* vx, void* vy, void* vz, uint32_t* m_state,
@@ -983,6 +1033,10 @@ int trmc_destroy(trmc_ctx* c)
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->side) (void)hipStreamDestroy(c->side);
+    for (int i = 0; i < trmc_ctx::kStage; ++i) {
+        if (c->stage_ev[i]) (void)hipEventDestroy(c->stage_ev[i]);
+        if (c->stage[i]) (void)hipHostFree(c->stage[i]);
+    }
     delete c;
     return e == hipSuccess ? 0 : TRMC_EIO;
 }

@@ -5,8 +5,11 @@ counts) arrive over time.  All running requests share one context and advance
 together, one step per tick (one trmc_step over every active instance).  At each
 tick boundary the loop
 
-  * retires the requests whose last step has run (their moments are read and
-    their device memory is released),
+  * retires the requests whose last step has run: their moments are written by
+    the device into pinned host memory behind the step (trmc_moments_async), the
+    slot leaves the active set at once, and the request's device memory is
+    released when an event recorded after the copy has passed (checked at every
+    tick, so the host never waits for the device to drain),
   * admits waiting requests in arrival order while the HBM budget (particle
     arrays plus library workspace of the running requests) and the slot and
     cell capacities allow,
@@ -30,7 +33,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _abi
-from . import (ADAPTIVE, FP32_MIXED, FP64, HOMOG, SLAB1D, Context, Instance, check)
+from . import (ADAPTIVE, FP32_MIXED, FP64, HOMOG, SLAB1D, Context, Instance, check, moments_record_bytes,
+               unpack_moments)
 
 
 def instance_of(req, precision=FP32_MIXED, m_cap=64) -> Instance:
@@ -92,6 +96,10 @@ class Server:
         self.used = 0
         self.cells = 0
         self.active = {}  # slot -> [req, steps_left, bytes, t_admit, tensors, tick_admit]
+        # retired requests whose results are on their way to the host:
+        # [req, bytes, t_admit, tensors, tick_admit, host buffer, event]
+        self.draining = deque()
+        self.pinned = []  # free pinned host buffers for the results
         self.peak_bytes = 0
         self.peak_active = 0
         self.ticks = 0
@@ -136,23 +144,63 @@ class Server:
         self.peak_active = max(self.peak_active, len(self.active))
         return slot
 
-    def retire(self, slot, t0):
-        req, _, nbytes, t_adm, _, tick = self.active[slot]
-        mom = self.ctx.moments(slot)  # synchronises: the results are on the host
-        state = self.ctx.read(slot) if req["rid"] in self.capture else None
-        t = time.perf_counter() - t0
-        self.ctx.retire(slot)
-        del self.active[slot]
-        self.used -= nbytes
+    def _done(self, req, t_adm, tick, t, mom, state):
         self.cells -= int(req["n_cells"]) if req["slab"] else 1
         sz = 4 if self.precision == FP32_MIXED else 8
         per = (8 if req["slab"] else 6) * sz * int(req["n"])
         return Done(req["rid"], int(req["n"]), int(req["steps"]), req["arrival"], t_adm, t, mom, state, tick, per)
 
-    def run(self, requests, realtime: bool = True, log=None):
+    def retire(self, slot, t0):
+        """Take a finished request out of the active set.  Its results are copied
+        behind its last step; harvest() returns the request once they are on the
+        host.  (A request whose final particles are captured is read at once.)"""
+        import torch
+        req, _, nbytes, t_adm, parts, tick = self.active.pop(slot)
+        if req["rid"] in self.capture:
+            mom = self.ctx.moments(slot)  # synchronises: the results are on the host
+            state = self.ctx.read(slot)
+            t = time.perf_counter() - t0
+            self.ctx.retire(slot)
+            self.used -= nbytes
+            return self._done(req, t_adm, tick, t, mom, state)
+        nc = int(req["n_cells"]) if req["slab"] else 1
+        need = moments_record_bytes(nc)
+        buf = None
+        for k, b in enumerate(self.pinned):
+            if b.numel() >= need:
+                buf = self.pinned.pop(k)
+                break
+        if buf is None:
+            buf = torch.empty(max(need, 1 << 16), dtype=torch.uint8, pin_memory=True)
+        self.ctx.moments_async(slot, buf)
+        ev = torch.cuda.Event()
+        ev.record(self.ctx.stream)
+        self.ctx.retire(slot)  # the next step leaves it out; its memory lives until ev
+        self.draining.append([req, nbytes, t_adm, parts, tick, buf, ev])
+        return None
+
+    def harvest(self, t0, wait=False):
+        """Requests whose results have reached the host (in retirement order);
+        wait: block for all of them."""
+        out = []
+        while self.draining and (wait or self.draining[0][6].query()):
+            req, nbytes, t_adm, parts, tick, buf, ev = self.draining.popleft()
+            ev.synchronize()
+            nc = int(req["n_cells"]) if req["slab"] else 1
+            mom = unpack_moments(buf, nc)
+            t = time.perf_counter() - t0
+            self.pinned.append(buf)
+            self.used -= nbytes
+            out.append(self._done(req, t_adm, tick, t, mom, None))
+        return out
+
+    def run(self, requests, realtime: bool = True, log=None, ahead: int = 2):
         """Serve the requests (sorted by arrival).  realtime: arrivals follow the
         wall clock (idle gaps are waited out); otherwise every request is queued
-        at time 0.  Returns the list of Done records in completion order."""
+        at time 0.  ahead: ticks the host may run ahead of the device (it prepares
+        the next tick while the device runs the current one, and admissions join
+        at most that many ticks later).  Returns the list of Done records in
+        completion order."""
         import torch
         ticks_ev = []  # (start, end) events of every tick on the context's stream
         pending = deque(sorted(requests, key=lambda r: r["arrival"]))
@@ -160,7 +208,8 @@ class Server:
         done = []
         t0 = time.perf_counter()
         head = None  # (inst, bytes) of waiting[0]
-        while pending or waiting or self.active:
+        while pending or waiting or self.active or self.draining:
+            done.extend(self.harvest(t0))
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0]["arrival"] <= now):
                 r = pending.popleft()
@@ -173,13 +222,15 @@ class Server:
                     head = self.cost(waiting[0])
                 inst, nbytes = head
                 if not self.fits(waiting[0], nbytes):
-                    if not self.active:
+                    if not self.active and not self.draining:
                         raise RuntimeError(f"request {waiting[0]['rid']} does not fit in an empty server")
                     break
                 self.admit(waiting.popleft(), inst, nbytes, now)
                 head = None
             if not self.active:
-                if pending:
+                if self.draining:
+                    done.extend(self.harvest(t0, wait=True))
+                elif pending:
                     time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
                 continue
             ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -188,13 +239,17 @@ class Server:
             ev[1].record(self.ctx.stream)
             ticks_ev.append(ev)
             self.ticks += 1
+            if len(ticks_ev) > ahead:
+                ticks_ev[-1 - ahead][1].synchronize()
             finished = []
             for slot, st in self.active.items():
                 st[1] -= 1
                 if st[1] == 0:
                     finished.append(slot)
             for slot in finished:
-                done.append(self.retire(slot, t0))
+                d = self.retire(slot, t0)
+                if d is not None:
+                    done.append(d)
             if log and finished:
                 log(f"t={time.perf_counter() - t0:.3f}s tick {self.ticks}: {len(finished)} done, "
                     f"{len(self.active)} running, {len(waiting)} waiting, {self.used / 2**30:.2f} GiB")
