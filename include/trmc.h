@@ -16,7 +16,10 @@
  *     the context unchanged.  Errors of asynchronous GPU work surface at the next
  *     synchronising call (trmc_sync, trmc_moments, trmc_read).
  *   - Device memory is never allocated or freed by the library: particle arrays
- *     and workspaces are owned by the caller and must outlive the context.
+ *     and workspaces are owned by the caller and must outlive the context.  The
+ *     context owns only host-side objects: a second stream and its events, the
+ *     captured graph, and a ring of pinned host staging buffers for its uploads
+ *     (grown on demand, freed by trmc_destroy).
  *   - Work is enqueued on the HIP stream given at creation; calls on one context
  *     must come from one host thread at a time.
  *   - Results depend only on (descriptor, initial particles, number of steps):
