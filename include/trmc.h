@@ -220,7 +220,8 @@ int trmc_retire(trmc_ctx* ctx, uint32_t slot);
  * FP64 cell sums.  Synchronises the stream; TRMC_EINVAL on an unknown path. */
 #define TRMC_SCHED_BUCKETS 32
 #define TRMC_PATH_DEFAULT 0u /* library rule: homogeneous cells WAVE below 1024 particles, TILED from
-                              * 65536 on, GROUP between; slab cells WAVE up to 4096, GROUP above */
+                              * 65536 on, GROUP between; cells of a slab of at least 2048 cells WAVE
+                              * up to 4096 particles, GROUP otherwise */
 #define TRMC_PATH_GROUP 1u   /* one 512-thread workgroup per cell */
 #define TRMC_PATH_WAVE 2u    /* one 64-lane wave per cell, eight cells per workgroup */
 #define TRMC_PATH_TILED 3u   /* tile kernels over the cell's slots plus per-cell tree kernels */

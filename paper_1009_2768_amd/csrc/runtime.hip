@@ -57,6 +57,7 @@ using namespace trmc;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr uint32_t kWaveSlabCells = 2048;  // fewest cells of a slab whose small cells default to WAVE
 size_t al(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
@@ -293,7 +294,9 @@ int rebuild_tables(trmc_ctx* c)
         while (bucket + 1 < TRMC_SCHED_BUCKETS && per >= (double)(2ull << bucket)) ++bucket;
         uint32_t path = c->sched[bucket];
         if (path == TRMC_PATH_DEFAULT) {
-            if (slab) path = per <= (double)kSmallCell ? TRMC_PATH_WAVE : TRMC_PATH_GROUP;
+            // a slab of fewer than kWaveSlabCells cells would fill too few workgroups
+            // at eight cells each: one workgroup per cell instead
+            if (slab) path = per <= (double)kSmallCell && nc >= kWaveSlabCells ? TRMC_PATH_WAVE : TRMC_PATH_GROUP;
             else if (per < (double)kSmallHomog) path = TRMC_PATH_WAVE;
             else path = per >= (double)kTiledCell ? TRMC_PATH_TILED : TRMC_PATH_GROUP;
         }
