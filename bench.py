@@ -390,12 +390,13 @@ def serving(T, args):
     table, _ = srv.tune(reqs, log=log)  # outside the served stream
     names = ["default", "group", "wave", "tiled"]
     log(f"serving schedule tuned in {time.time() - t0:.1f} s")
-    done = srv.run(reqs, realtime=True)
+    done = srv.run(reqs, realtime=True, ahead=args.serve_ahead)
     srv.close()
     out = summarize(done, srv.wall, srv.busy)
     out.update({"rate_per_s": args.serve_rate, "stream_s": args.serve_seconds,
                 "hbm_budget_gib": args.serve_budget_gib, "peak_hbm_gib": srv.peak_bytes / 2**30,
                 "peak_running": srv.peak_active, "ticks": srv.ticks, "precision": "fp32",
+                "ticks_ahead": args.serve_ahead,
                 "schedule": {f"2^{b}": names[p] for b, p in enumerate(table) if p},
                 "mix": "homogeneous (Maxwell) and Sod tubes (hard spheres) 50/50, N log-uniform [1e3, 1e6], "
                        "50-500 steps, eps log-uniform [1e-4, 1]"})
@@ -430,6 +431,7 @@ def main():
     ap.add_argument("--speedup-stride", type=int, default=16,
                     help="compare batched and one-at-a-time stepping on every n-th instance (0 = skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="HBM budget of the running requests")
+    ap.add_argument("--serve-ahead", type=int, default=2, help="ticks the serving host may run ahead of the GPU")
     ap.add_argument("--no-reuse", action="store_true",
                     help="skip the run of the workload with the adaptive depth that keeps rejected attempts")
     ap.add_argument("--no-shock", action="store_true", help="skip the stationary-shock run")
