@@ -249,10 +249,11 @@ int stage_uploads(trmc_ctx* c, const Uploads& u)
     c->stage_next = (i + 1) % trmc_ctx::kStage;
     if (c->stage_used[i] && hipEventSynchronize(c->stage_ev[i]) != hipSuccess) return TRMC_EIO;
     if (c->stage_cap[i] < u.blob.size()) {
+        // grow to at least twice the old size (and 64 KiB), so that growth is rare
+        const size_t want = std::max(u.blob.size(), std::max<size_t>(size_t(1) << 16, 2 * c->stage_cap[i]));
         if (c->stage[i]) (void)hipHostFree(c->stage[i]);
         c->stage[i] = nullptr;
         c->stage_cap[i] = 0;
-        const size_t want = std::max(u.blob.size(), std::max<size_t>(size_t(1) << 16, 2 * c->stage_cap[i]));
         void* p = nullptr;
         if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return TRMC_EIO;
         c->stage[i] = static_cast<unsigned char*>(p);
