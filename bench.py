@@ -104,6 +104,21 @@ def stored_traffic(kernel: str, table, steps_per_launch: int = 1):
     return rec["bytes_per_launch"]
 
 
+def traffic_record(kernel: str):
+    """The committed counter record itself (bytes per launch, steps per launch,
+    schedule) while the kernel sources match it, else None: reported beside a
+    run of another number of steps per launch, whose own launch was not counted."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_sha256() or kernel not in rec.get("kernel", ""):
+        return None
+    return {"bytes_per_launch": rec["bytes_per_launch"], "steps_per_launch": rec.get("steps_per_launch", 1),
+            "schedule": rec.get("table")}
+
+
 def time_steps(ctx, steps, warmup, fuse):
     """`warmup` untimed steps, then exactly `steps` timed steps on the context's
     stream, synchronised on both sides.  fuse: one call for all the timed steps
@@ -521,6 +536,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_schedule": json.load(open(TRAFFIC_RECORD))["table"] if traffic else None,
+                     "traffic_counted": None if tiled else traffic_record(kernel),
                      "steps_per_launch": per_launch,
                      "kernel": (kernel + " (+ k_advance, about 4 us)") if not tiled else
                      "tile pipeline + " + kernel + " (several kernels per step)"},
