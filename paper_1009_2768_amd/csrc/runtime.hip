@@ -56,6 +56,11 @@ using namespace trmc;
 
 namespace {
 
+// The whole-cell kernels are built and tested with 512-thread workgroups only:
+// a 256-thread build made a memory fault in the kernel of the adaptive depth
+// with reuse, whose cause was not found.
+static_assert(kCollideThreads == 512, "the whole-cell kernels support 512-thread workgroups only");
+
 constexpr size_t kAlign = 256;
 constexpr uint32_t kWaveSlabCells = 2048;  // fewest cells of a slab whose small cells default to WAVE
 size_t al(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
