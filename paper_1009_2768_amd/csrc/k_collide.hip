@@ -603,8 +603,15 @@ __global__ __launch_bounds__(kCollideThreads) void k_collide_reuse<double>(const
     collide_entry<double, true>(big, n_big, lv_big, small, n_small, lv_small, nsteps);
 }
 
+// The FP64 kernel's natural register count (about 250) leaves two waves per
+// SIMD; held to TRMC_F64_WAVES_PER_EU it spills a few hundred bytes per lane
+// and runs faster.
+#ifndef TRMC_F64_WAVES_PER_EU
+#define TRMC_F64_WAVES_PER_EU 4
+#endif
 template <>
-__global__ __launch_bounds__(kCollideThreads) void k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(TRMC_F64_WAVES_PER_EU, 8))) void
+k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,
                                                                      uint32_t lv_big,
                                                                      const CellRef* __restrict__ small,
                                                                      uint32_t n_small, uint32_t lv_small,
