@@ -99,3 +99,28 @@ def test_stored_traffic_needs_matching_sources(tmp_path, monkeypatch):
     # the stored figure is reported only for the kernel sources it was measured on
     monkeypatch.setattr(bench, "source_sha256", lambda: "0" * 64)
     assert bench.stored_traffic("k_collide<float>", None) is None
+
+
+def test_unpack_moments_reads_the_abi_records(T):
+    """The records trmc_moments_async writes (trmc_cell_moments, as laid out in
+    the header) decode into the same dict as Context.moments."""
+    import ctypes
+
+    from paper_1009_2768_amd import _abi
+    nc = 3
+    recs = (_abi.CellMoments * nc)()
+    for c in range(nc):
+        recs[c].n = 100 + c
+        recs[c].m_state = 2 * c + 1
+        recs[c].rho = 0.5 * c
+        recs[c].M4 = 15.0 + c
+        recs[c].collisions = (1 << 40) + c
+        recs[c].wb_thermalized = 7 * c
+        recs[c].q = 1.0 / (c + 2)
+    raw = np.frombuffer(bytes(recs), dtype=np.uint8)
+    assert T.moments_record_bytes(nc) == len(raw) == nc * ctypes.sizeof(_abi.CellMoments)
+    got = T.unpack_moments(np.concatenate([raw, np.zeros(40, np.uint8)]), nc)  # longer buffer: first nc
+    assert sorted(got) == sorted(f[0] for f in _abi.CellMoments._fields_)
+    for c in range(nc):
+        for name, _ in _abi.CellMoments._fields_:
+            assert got[name][c] == getattr(recs[c], name), (c, name)
