@@ -235,9 +235,11 @@ int trmc_get_schedule(const trmc_ctx* ctx, uint32_t* paths, uint32_t n_buckets);
  * kernel directly.  Both enqueue the same kernels with the same arguments. */
 int trmc_use_graph(trmc_ctx* ctx, int on);
 
-/* on != 0 (the default): trmc_step fuses the steps of a call when it can (see
- * trmc_step); on == 0: one step after another, each its own launches (or graph
- * replay).  Results do not depend on it. */
+/* Batching (a scheduling choice, not a passage of the paper: the step of a
+ * space-homogeneous instance, eq. HOM-r, has no transport, so each cell's next
+ * step reads only that cell).  on != 0 (the default): trmc_step fuses the steps
+ * of a call when it can (see trmc_step); on == 0: one step after another, each
+ * its own launches (or graph replay).  Results do not depend on it. */
 int trmc_fuse_steps(trmc_ctx* ctx, int on);
 
 /* Wait for the stream and report any asynchronous error. */
