@@ -7,6 +7,12 @@ or bi-Maxwellian initial data, dt = 0.05, adaptive depth (m_init 2, m_cap 64,
 delta1 0.005, delta2 0.01).  A step is one collision step of every instance; the
 metric is particle-steps per second over the timed steps (state resident in HBM).
 
+The headline (value, roofline) is measured first.  Then, by default, the legs
+cpu (the oracle on host threads), batching (batched against one instance at a
+time) and serving (a Poisson request stream, and the same requests all queued
+at once); --legs adds fusion, reuse, shock, tubes and wb.  A watchdog prints the
+line after --budget seconds with the legs not reached listed as skipped.
+
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -161,13 +167,38 @@ def time_steps(ctx, steps, warmup, fuse):
     return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
 
-def cpu_baseline(N, eps, alpha, init, seed, budget_s=15.0):
-    """The FP64 oracle on a bounded sample of the same batch: every 64th instance,
-    stepped round after round (one step of each sampled instance per round) until
-    the time budget is spent."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores(cap: int = 16) -> int:
+    """Host cores this process may use, at most `cap` (a GPU machine shares its host
+    between GPUs: 16 cores per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
+
+
+def cpu_baseline(N, eps, alpha, init, seed, budget_s=15.0, stride=16):
+    """The FP64 oracle on a bounded sample of the same batch: every stride-th
+    instance, spread over host threads (the oracle is C called through ctypes,
+    which releases the interpreter lock, and its instances share nothing).  Each
+    thread steps its instances round after round until the time budget is spent;
+    the rate is all particle-steps done over the wall time."""
+    import threading
+
     import oracle
     import workloads as W
-    idx = list(range(0, len(N), 64))
+    idx = list(range(0, len(N), stride))
     insts = []
     for i in idx:
         n = int(N[i])
@@ -175,17 +206,38 @@ def cpu_baseline(N, eps, alpha, init, seed, budget_s=15.0):
         insts.append(oracle.Instance(a[0], a[1], a[2], eps=float(eps[i]), alpha=float(alpha[i]), dt=0.05,
                                      trunc=oracle.ADAPTIVE, m_init=2, m_cap=64, uid=i, seed=seed,
                                      weight=1.0 / n))
-    done_ps, t_used, rounds = 0, 0.0, 0
-    while t_used < budget_s:
-        for inst in insts:
-            t0 = time.perf_counter()
-            inst.run(1)
-            t_used += time.perf_counter() - t0
-            done_ps += inst.n
-        rounds += 1
-    return {"value": done_ps / t_used, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rounds} steps of {len(insts)} instances (every 64th of the batch, "
-                      f"{sum(i.n for i in insts)} particles), serial FP64 oracle on one core, {t_used:.1f} s"}
+    oracle.lib()
+    cores = host_cores()
+    # deal the instances to threads largest first, each to the least loaded thread
+    shares = [[] for _ in range(cores)]
+    load = [0] * cores
+    for k in sorted(range(len(insts)), key=lambda k: -insts[k].n):
+        t = load.index(min(load))
+        shares[t].append(insts[k])
+        load[t] += insts[k].n
+    done = [0] * cores
+    steps = [0] * cores
+    t_end = time.perf_counter() + budget_s
+
+    def work(t):
+        while time.perf_counter() < t_end:
+            for inst in shares[t]:
+                inst.run(1)
+                done[t] += inst.n
+            steps[t] += 1
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=work, args=(t,)) for t in range(cores) if shares[t]]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    wall = time.perf_counter() - t0
+    return {"value": sum(done) / wall, "unit": "particle-steps/s", "cores": len(th), "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{len(insts)} instances (every {stride}th of the batch, {sum(i.n for i in insts)} "
+                      f"particles), {min(steps)}-{max(steps)} steps each, serial FP64 oracle per instance on "
+                      f"{len(th)} host threads, {wall:.1f} s"}
 
 
 def batching_speedup(T, N, eps, alpha, init, seed, prec, table, stride=16, steps=3):
@@ -393,32 +445,77 @@ def tubes(T, seed, steps=20, warmup=5):
 
 
 def serving(T, args):
-    """Serving run: a Poisson stream of homogeneous solves and shock tubes (N
+    """Serving: a Poisson stream of homogeneous solves and shock tubes (N
     log-uniform in [1e3, 1e6], 50-500 steps, eps log-uniform in [1e-4, 1]) served
-    with continuous batching under an HBM budget, arrivals in real time."""
+    with continuous batching under an HBM budget, arrivals in real time; then the
+    same requests all queued at time 0 (the saturation run: the served form's
+    throughput when the GPU never waits for arrivals)."""
+    import torch
+
     import workloads as W
     from paper_1009_2768_amd.serve import Server, summarize
     reqs = W.serving_requests(args.serve_rate, args.serve_seconds, seed=args.seed)
     log(f"serving {len(reqs)} requests over {args.serve_seconds} s ...")
-    srv = Server(hbm_budget=int(args.serve_budget_gib * 2**30), max_instances=4096, max_cells=1 << 21)
-    t0 = time.time()
-    table, _ = srv.tune(reqs, log=log)  # outside the served stream
     names = ["default", "group", "wave", "tiled"]
-    log(f"serving schedule tuned in {time.time() - t0:.1f} s")
-    done = srv.run(reqs, realtime=True, ahead=args.serve_ahead)
-    srv.close()
-    out = summarize(done, srv.wall, srv.busy)
-    out.update({"rate_per_s": args.serve_rate, "stream_s": args.serve_seconds,
-                "hbm_budget_gib": args.serve_budget_gib, "peak_hbm_gib": srv.peak_bytes / 2**30,
-                "peak_running": srv.peak_active, "ticks": srv.ticks, "precision": "fp32",
-                "ticks_ahead": args.serve_ahead,
-                "schedule": {f"2^{b}": names[p] for b, p in enumerate(table) if p},
-                "mix": "homogeneous (Maxwell) and Sod tubes (hard spheres) 50/50, N log-uniform [1e3, 1e6], "
-                       "50-500 steps, eps log-uniform [1e-4, 1]"})
-    log(f"serving: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
-        f"{out['particle_steps_per_s']:.3e} particle-steps/s, wall {srv.wall:.2f} s, device busy "
-        f"{srv.busy:.2f} s, HBM fraction {out['hbm_frac_wall']:.4f} (wall) {out['hbm_frac_busy']:.4f} (busy)")
+    out = {"rate_per_s": args.serve_rate, "stream_s": args.serve_seconds, "hbm_budget_gib": args.serve_budget_gib,
+           "precision": "fp32", "ticks_ahead": args.serve_ahead,
+           "mix": "homogeneous solves (Maxwell / hard spheres 50/50, BKW / bi-Maxwellian 50/50) and Sod tubes "
+                  "(hard spheres, 888 / 111 particles per cell) 50/50, N log-uniform [1e3, 1e6], 50-500 steps, "
+                  "eps log-uniform [1e-4, 1]"}
+    table = None
+    for name, realtime in (("poisson", True), ("saturation", False)):
+        srv = Server(hbm_budget=int(args.serve_budget_gib * 2**30), max_instances=4096, max_cells=1 << 21)
+        if table is None:
+            t0 = time.time()
+            table, _ = srv.tune(reqs, log=log)  # outside the served stream
+            log(f"serving schedule tuned in {time.time() - t0:.1f} s")
+            out["schedule"] = {f"2^{b}": names[p] for b, p in enumerate(table) if p}
+        else:
+            srv.ctx.set_schedule(table)
+        done = srv.run(reqs, realtime=realtime, ahead=args.serve_ahead)
+        srv.close()
+        res = summarize(done, srv.wall, srv.busy)
+        res.update({"peak_hbm_gib": srv.peak_bytes / 2**30, "peak_running": srv.peak_active, "ticks": srv.ticks})
+        out[name] = res
+        log(f"serving {name}: p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, "
+            f"{res['particle_steps_per_s']:.3e} particle-steps/s, wall {srv.wall:.2f} s, device busy "
+            f"{srv.busy:.2f} s, HBM fraction {res['hbm_frac_wall']:.4f} (wall) {res['hbm_frac_busy']:.4f} (busy)")
+        del srv, done
+        torch.cuda.empty_cache()
+    # the headline figures of the served form: latency at the stated rate, HBM
+    # fraction over the device-busy time and at saturation
+    out.update({"p50_ms": out["poisson"]["p50_ms"], "p99_ms": out["poisson"]["p99_ms"],
+                "particle_steps_per_s": out["poisson"]["particle_steps_per_s"],
+                "hbm_frac_busy": out["poisson"]["hbm_frac_busy"],
+                "saturation_particle_steps_per_s": out["saturation"]["particle_steps_per_s"],
+                "saturation_hbm_frac": out["saturation"]["hbm_frac_wall"]})
     return out
+
+
+LEGS_DEFAULT = ("cpu", "batching", "serving")
+LEGS_ALL = LEGS_DEFAULT + ("fusion", "reuse", "shock", "tubes", "wb")
+
+
+class Line:
+    """The one JSON line: filled leg by leg, printed once (at the end, or by the
+    watchdog when the run outlives its time budget, with the legs not reached
+    listed under "skipped")."""
+
+    def __init__(self):
+        import threading
+        self.d = {}
+        self.lock = threading.Lock()
+        self.printed = False
+        self.pending = []
+
+    def emit(self):
+        with self.lock:
+            if self.printed:
+                return
+            self.printed = True
+            if self.pending:
+                self.d["skipped"] = list(self.pending)
+            print(json.dumps(self.d), flush=True)
 
 
 def main():
@@ -429,7 +526,11 @@ def main():
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default=",".join(LEGS_DEFAULT),
+                    help="legs after the headline, comma-separated, from: " + ",".join(LEGS_ALL) +
+                         " ('all' for every one, 'none' for the headline only)")
+    ap.add_argument("--budget", type=float, default=420.0,
+                    help="seconds after which the line is printed with the legs not yet run listed as skipped")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--path", choices=["auto", "default", "group", "wave", "tiled"], default="auto",
                     help="kernel path per cell: auto = autotuned per size bucket (outside the timed region)")
@@ -438,27 +539,24 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one instead of a HIP graph")
     ap.add_argument("--no-fuse", action="store_true",
                     help="one launch per step instead of one launch taking every cell through all timed steps")
-    ap.add_argument("--no-fuse-compare", action="store_true",
-                    help="skip the timing of the same steps one launch per step on a twin context")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
-                    help="length of the Poisson request stream of the serving run (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of the Poisson request stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--speedup-stride", type=int, default=16,
-                    help="compare batched and one-at-a-time stepping on every n-th instance (0 = skip)")
+                    help="compare batched and one-at-a-time stepping on every n-th instance")
     ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="HBM budget of the running requests")
     ap.add_argument("--serve-ahead", type=int, default=2, help="ticks the serving host may run ahead of the GPU")
-    ap.add_argument("--no-reuse", action="store_true",
-                    help="skip the run of the workload with the adaptive depth that keeps rejected attempts")
-    ap.add_argument("--no-shock", action="store_true", help="skip the stationary-shock run")
-    ap.add_argument("--no-tubes", action="store_true", help="skip the Sod and transition-regime tube runs")
-    ap.add_argument("--wb-instances", type=int, default=64,
-                    help="instances of the tree-shape truncation comparison (0 = skip)")
+    ap.add_argument("--wb-instances", type=int, default=64, help="instances of the tree-shape truncation leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB each (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
+    legs = [] if args.legs == "none" else list(LEGS_ALL) if args.legs == "all" else \
+        [s for s in args.legs.split(",") if s]
+    for s in legs:
+        if s not in LEGS_ALL:
+            ap.error(f"unknown leg {s}")
 
     import numpy as np
     import torch
@@ -472,6 +570,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
         return
+
+    t_start = time.time()
+    out = Line()
 
     import paper_1009_2768_amd as T
     T.load()
@@ -501,6 +602,7 @@ def main():
     if not args.no_graph:
         ctx.use_graph(True)
     fuse = not args.no_fuse
+    log(f"timing {args.steps} steps after {args.warmup} ...")
     wall, avg_ms = time_steps(ctx, args.steps, args.warmup, fuse)
     ms_per_step = wall * 1000.0 / args.steps
     value = total * args.steps / wall
@@ -515,7 +617,11 @@ def main():
     per_launch = args.steps if fuse else 1
     traffic = None if tiled else stored_traffic(kernel, table, per_launch)
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, kernel events {avg_ms:.3f} ms")
-    line = {
+    work = work_totals(T, ctx)
+    ctx.close()
+    del ctx, bufs
+    torch.cuda.empty_cache()
+    out.d.update({
         "metric": "particle-collision-step updates/sec",
         "value": value,
         "unit": "particle-steps/s",
@@ -540,38 +646,60 @@ def main():
                      "steps_per_launch": per_launch,
                      "kernel": (kernel + " (+ k_advance, about 4 us)") if not tiled else
                      "tile pipeline + " + kernel + " (several kernels per step)"},
-    }
-    recompute_work = work_totals(T, ctx) if not args.no_reuse else None
-    ctx.close()
-    del ctx, bufs
-    torch.cuda.empty_cache()
-    if fuse and not args.no_fuse_compare:
-        log("the same steps, one launch per step ...")
-        line["step_fusion"] = step_fusion(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup,
-                                          ms_per_step)
-        log(f"step fusion: {line['step_fusion']}")
-    if not args.no_reuse:
-        log("adaptive depth keeping rejected attempts ...")
-        reuse = adaptive_reuse(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup, fuse)
-        line["adaptive_reuse"] = {"recompute": dict(ms_per_step=ms_per_step, kernel_ms=avg_ms, **recompute_work),
-                                  "reuse": reuse, "speedup": ms_per_step / reuse["ms_per_step"]}
-        log(f"adaptive reuse: {line['adaptive_reuse']}")
-    if args.speedup_stride > 0:
-        log("batched versus one instance at a time ...")
-        line["batching"] = batching_speedup(T, N, eps, alpha, init, args.seed, prec, table, args.speedup_stride)
-        log(f"batching: {line['batching']}")
-    if not args.no_shock:
-        line["stationary_shock"] = stationary_shock(T, args.seed)
-    if not args.no_tubes:
-        line["tubes"] = tubes(T, args.seed)
-    if args.wb_instances > 0:
-        line["tree_shape_truncation"] = tree_shape_truncation(T, args.wb_instances, args.seed)
-    if args.serve_seconds > 0:
-        line["serving"] = serving(T, args)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(N, eps, alpha, init, args.seed, args.cpu_budget)
-    print(json.dumps(line), flush=True)
+        "work_last_step": work,
+    })
+    log(f"headline: {value:.4e} particle-steps/s, roofline frac {achieved / HBM_PEAK_GBS:.4f}")
+
+    # legs after the headline; the watchdog prints the line if they outlive the budget
+    import threading
+    out.pending = list(legs)
+
+    def watchdog():
+        log(f"time budget of {args.budget:.0f} s spent; printing the line without {out.pending}")
+        out.emit()
+        os._exit(0)
+
+    left = args.budget - (time.time() - t_start)
+    timer = threading.Timer(max(1.0, left), watchdog)
+    timer.daemon = True
+    timer.start()
+    for leg in legs:
+        log(f"leg {leg} ...")
+        t0 = time.time()
+        if leg == "cpu":
+            res = cpu_baseline(N, eps, alpha, init, args.seed, args.cpu_budget)
+            out.d["cpu_baseline"] = res
+        elif leg == "batching":
+            res = batching_speedup(T, N, eps, alpha, init, args.seed, prec, table, args.speedup_stride)
+            out.d["batching"] = res
+        elif leg == "serving":
+            res = serving(T, args)
+            out.d["serving"] = res
+        elif leg == "fusion":
+            if not fuse:
+                res = {"skipped": "steps are not fused on this schedule"}
+            else:
+                res = step_fusion(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup,
+                                  ms_per_step)
+            out.d["step_fusion"] = res
+        elif leg == "reuse":
+            reuse = adaptive_reuse(T, N, eps, alpha, init, args.seed, prec, table, args.steps, args.warmup, fuse)
+            res = {"recompute": dict(ms_per_step=ms_per_step, kernel_ms=avg_ms, **work),
+                   "reuse": reuse, "speedup": ms_per_step / reuse["ms_per_step"]}
+            out.d["adaptive_reuse"] = res
+        elif leg == "shock":
+            res = stationary_shock(T, args.seed)
+            out.d["stationary_shock"] = res
+        elif leg == "tubes":
+            res = tubes(T, args.seed)
+            out.d["tubes"] = res
+        elif leg == "wb":
+            res = tree_shape_truncation(T, args.wb_instances, args.seed)
+            out.d["tree_shape_truncation"] = res
+        out.pending.remove(leg)
+        log(f"leg {leg} done in {time.time() - t0:.1f} s: {res}")
+    timer.cancel()
+    out.emit()
 
 
 if __name__ == "__main__":

@@ -78,6 +78,60 @@ def test_served_results_equal_alone(T, prec):
         assert np.array_equal(np.asarray(mom["collisions"]), np.asarray(by[rid].moments["collisions"]))
 
 
+def test_served_fp64_requests_match_oracle(T, orc):
+    """Requests served in a mix (FP64) against the oracle run from the same
+    initial particles (read back from the device recipe): integers of the last
+    step exact, velocities within 1e-12 of the cell's thermal speed, positions
+    within 1e-12 of the cell width."""
+    import math
+
+    import torch
+    from paper_1009_2768_amd.serve import Server, instance_of
+    reqs = W.serving_requests(rate=60.0, duration=0.3, seed=4, n_min=500, n_max=20000, steps_min=3,
+                              steps_max=10, ppc_left=64)
+    probe = [r["rid"] for r in reqs[:: max(1, len(reqs) // 6)]]
+    say(f"serving {len(reqs)} requests (fp64) against the oracle, probes {probe}")
+    srv = Server(hbm_budget=0, precision=T.FP64, max_instances=64, max_cells=1 << 16, capture=probe)
+    costs = [srv.cost(r)[1] for r in reqs]
+    srv.budget = int(max(max(costs), 3 * np.mean(costs)))
+    done = srv.run(reqs, realtime=False)
+    srv.close()
+    by = {d.rid: d for d in done}
+    kinds = set()
+    for rid in probe:
+        req = next(r for r in reqs if r["rid"] == rid)
+        inst = instance_of(req, T.FP64)
+        a = {k: (v.cpu().numpy() if v is not None else None)
+             for k, v in W.serving_initial(req, dtype=torch.float64).items()}
+        kw = dict(seed=inst.seed, uid=inst.uid, dt=inst.dt, eps=inst.eps, alpha=inst.alpha, trunc=inst.trunc,
+                  m_init=inst.m_init, m_cap=inst.m_cap, delta1=inst.delta1, delta2=inst.delta2,
+                  length=inst.length, weight=inst.particle_weight)
+        if req["slab"]:
+            kw.update(geometry=orc.SLAB, n_cells=inst.n_cells, x=a["x"])
+        o = orc.Instance(a["vx"], a["vy"], a["vz"], **kw)
+        o.run(int(req["steps"]))
+        got, mom = by[rid].state, by[rid].moments
+        nc = inst.n_cells if req["slab"] else 1
+        kinds.add((req["slab"], inst.alpha))
+        for c in range(nc):
+            r = o.last[c]
+            assert int(mom["collisions"][c]) == int(r.collisions), (rid, c)
+            assert int(mom["thermalized"][c]) == int(r.n_th), (rid, c)
+            assert int(mom["m_used"][c]) == int(r.m_used), (rid, c)
+            assert int(mom["m_state"][c]) == int(o.m_state[c]), (rid, c)
+        if req["slab"]:
+            assert np.array_equal(np.asarray(mom["n"]), o.counts.astype(np.asarray(mom["n"]).dtype))
+            err = float(np.abs(got["x"] - o.x[:o.n]).max() * nc)
+            assert err <= 1e-12, (rid, "x", err)
+        ov = np.stack([o.vx[:o.n], o.vy[:o.n], o.vz[:o.n]], 1)
+        gv = np.stack([got["vx"], got["vy"], got["vz"]], 1)
+        Tc = ov.var(0).sum() / 3.0
+        err = float(np.abs(gv - ov).max() / math.sqrt(Tc))
+        assert err <= 1e-12, (rid, "v", err)
+    say(f"served requests matched the oracle: kinds (slab, alpha) {sorted(kinds)}")
+    assert (True, 1.0) in kinds and any(not s for s, _ in kinds)
+
+
 def test_request_larger_than_budget_is_rejected(T):
     from paper_1009_2768_amd.serve import Server
     reqs = W.serving_requests(rate=50.0, duration=0.1, seed=5, n_min=5000, n_max=6000, steps_min=2, steps_max=3)

@@ -62,8 +62,37 @@ def test_serving_stream_is_poisson_with_the_stated_ranges():
     for r in reqs:
         if r["slab"]:
             nc, left = r["n_cells"], r["n_cells"] // 2
-            assert 2 <= nc <= 12288
+            assert 2 <= nc <= 12288 and nc % 2 == 0
+            assert (r["ppc_left"], r["ppc_right"]) == (888, 111) and r["alpha"] == 1.0
             assert r["n"] == left * r["ppc_left"] + (nc - left) * r["ppc_right"]
+    # homogeneous solves: Maxwell molecules and hard spheres 50/50, BKW and bi-Maxwellian 50/50
+    hard = np.mean([r["alpha"] == 1.0 for r in homog])
+    assert abs(hard - 0.5) < 5 * math.sqrt(0.25 / len(homog))
+    bkw = np.mean([r["init"] == 0 for r in homog])
+    assert abs(bkw - 0.5) < 5 * math.sqrt(0.25 / len(homog))
+    # tubes of 888 / 111 particles per cell: n_cells = N / 499.5 up to rounding to an even count
+    for r in reqs:
+        if r["slab"] and r["n_cells"] > 2:
+            assert abs(r["n"] - r["n_cells"] * 499.5) <= 1.0
+
+
+def test_serving_initial_data_moments():
+    """Homogeneous serving requests start from BKW (K = 3/5: M4 = 12.6, T = 1) or
+    the bi-Maxwellian (P_xx = 2, T = 4/3); the draws are the device recipe, run on
+    the CPU here."""
+    import torch
+    n = 400_000
+    for init, m4, pxx in ((0, 12.6, 1.0), (1, None, 2.0)):
+        req = {"rid": 7 + init, "seed": 3, "slab": False, "n": n, "init": init}
+        p = W.serving_initial(req, device="cpu", dtype=torch.float64)
+        v = np.stack([p["vx"].numpy(), p["vy"].numpy(), p["vz"].numpy()])
+        e2 = (v * v).sum(0)
+        assert abs(v.mean(1)).max() < 5 * math.sqrt(2.0 / n)
+        assert abs((v[0] ** 2).mean() - pxx) < 5 * math.sqrt(8.0 / n)
+        if m4 is not None:
+            # E|v|^4 = 12.6; its variance for BKW at K = 0.6 is below 2000
+            assert abs(e2.var() + e2.mean() ** 2 - m4) < 5 * math.sqrt(2000.0 / n)
+            assert abs(e2.mean() - 3.0) < 5 * math.sqrt(20.0 / n)
 
 
 def test_serving_descriptors(T):
@@ -79,7 +108,7 @@ def test_serving_descriptors(T):
             assert inst.alpha == 1.0
         else:
             assert inst.geometry == T.HOMOG and math.isclose(inst.particle_weight, 1.0 / r["n"])
-            assert inst.alpha == 0.0
+            assert inst.alpha == r["alpha"] and r["alpha"] in (0.0, 1.0)
 
 
 def test_batched_workload_parameters():

@@ -172,18 +172,21 @@ def batched_velocities(N, init, seed: int = 0, K0: float = 0.6):
 
 def serving_requests(rate: float, duration: float, seed: int = 0, n_min: int = 1000, n_max: int = 1_000_000,
                      steps_min: int = 50, steps_max: int = 500, eps_min: float = 1e-4, eps_max: float = 1.0,
-                     slab_fraction: float = 0.5, ppc_left: int = 512):
+                     slab_fraction: float = 0.5, ppc_left: int = 888, ppc_right: int | None = None):
     """A Poisson request stream for the serving loop.
 
     Arrivals with exponential gaps of mean 1/rate over [0, duration); each request
-    is a homogeneous solve (Maxwell molecules, bi-Maxwellian or BKW-like initial
-    data) or a Sod-type shock tube (hard spheres), with N log-uniform in [n_min,
-    n_max], a step count uniform in [steps_min, steps_max] and eps log-uniform in
-    [eps_min, eps_max].  A tube has ppc_left particles per cell on its left half
-    and ppc_left / 8 on its right half (density ratio 0.125), so n_cells is about
-    N / (9 ppc_left / 16), kept within [2, 12288].
+    is a homogeneous solve (Maxwell molecules or hard spheres, 50/50; BKW or
+    bi-Maxwellian initial data, 50/50) or a Sod-type shock tube (hard spheres),
+    with N log-uniform in [n_min, n_max], a step count uniform in [steps_min,
+    steps_max] and eps log-uniform in [eps_min, eps_max].  A tube has ppc_left
+    particles per cell on its left half and ppc_right (default ppc_left / 8, the
+    density ratio 0.125) on its right half, and an even number of cells
+    n_cells = max(2, 2 round(N / (ppc_left + ppc_right))), so that its particle
+    count is close to N (888 / 111 particles per cell: n_cells = N / 499.5).
     """
     g = rng(seed, 11)
+    ppc_r = max(1, ppc_left // 8) if ppc_right is None else int(ppc_right)
     out, t, rid = [], 0.0, 0
     while True:
         t += g.exponential(1.0 / rate)
@@ -193,12 +196,12 @@ def serving_requests(rate: float, duration: float, seed: int = 0, n_min: int = 1
         steps = int(g.integers(steps_min, steps_max + 1))
         eps = float(eps_min * (eps_max / eps_min) ** g.random())
         slab = bool(g.random() < slab_fraction)
+        hard = bool(g.random() < 0.5)
         req = {"rid": rid, "arrival": t, "slab": slab, "steps": steps, "eps": eps, "seed": seed,
-               "alpha": 1.0 if slab else 0.0, "init": int(g.integers(0, 2))}
+               "alpha": 1.0 if (slab or hard) else 0.0, "init": int(g.integers(0, 2))}
         if slab:
-            nc = int(min(12288, max(2, round(n / (9 * ppc_left / 16)))))
+            nc = int(min(12288, max(2, 2 * round(n / (ppc_left + ppc_r)))))
             left = nc // 2
-            ppc_r = max(1, ppc_left // 8)
             req.update(n_cells=nc, ppc_left=ppc_left, ppc_right=ppc_r,
                        n=left * ppc_left + (nc - left) * ppc_r)
         else:
@@ -211,7 +214,9 @@ def serving_requests(rate: float, duration: float, seed: int = 0, n_min: int = 1
 def serving_initial(req, device="cuda", dtype=None):
     """Initial particles of a serving request, drawn on the device with a torch
     generator seeded by (seed, rid): deterministic for a given device, whether the
-    request runs alone or in a mix.  Returns dict(x, vx, vy, vz) of tensors."""
+    request runs alone or in a mix.  Tubes: the Sod states, positions uniform in
+    each cell; homogeneous solves: BKW (init 0) or bi-Maxwellian (init 1).
+    Returns dict(x, vx, vy, vz) of tensors."""
     import torch
     dtype = dtype or torch.float32
     gen = torch.Generator(device=device)
@@ -232,5 +237,13 @@ def serving_initial(req, device="cuda", dtype=None):
     if req["init"] == 1:  # bi-Maxwellian: means +-1 along x
         sign = torch.where(torch.arange(n, device=device) % 2 == 0, 1.0, -1.0).to(torch.float64)
         v[0] += sign
+    else:
+        # BKW at K = 3/5 (the recipe of bkw()): N(0, K I) with probability
+        # (5K - 3)/(2K), else radius sqrt(K chi2_5) in a uniform direction
+        K = 0.6
+        gauss = torch.rand(n, generator=gen, device=device, dtype=torch.float64) < (5.0 * K - 3.0) / (2.0 * K)
+        chi2 = torch.randn(5, n, generator=gen, device=device, dtype=torch.float64).square().sum(0)
+        d = v / v.norm(dim=0, keepdim=True).clamp_min(1e-300)
+        v = torch.where(gauss[None, :], v * math.sqrt(K), d * (K * chi2).sqrt()[None, :])
     return {"x": None, "vx": v[0].to(dtype).contiguous(), "vy": v[1].to(dtype).contiguous(),
             "vz": v[2].to(dtype).contiguous()}
