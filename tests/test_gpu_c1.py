@@ -45,35 +45,50 @@ def say(*a):
 @pytest.mark.parametrize("eps", [1.0, 0.1, 0.01])
 @pytest.mark.parametrize("trunc", ["natural", "adaptive"])
 def test_c1_every_step_matches_oracle(trmc, orc, eps, trunc):
+    """The oracle runs its 100 steps on a host thread (its C code releases the
+    interpreter lock) while the GPU runs and reads back every step."""
+    import threading
     T = trmc
     say("C1 trajectory", eps, trunc)
     vx, vy, vz = W.bkw(N, K0, seed=0, stream=0)
     tr = T.NATURAL if trunc == "natural" else T.ADAPTIVE
     m_cap = 2048 if trunc == "natural" else 64
+    o = orc.Instance(vx, vy, vz, eps=eps, alpha=0.0, trunc=orc.NATURAL if trunc == "natural" else orc.ADAPTIVE,
+                     m_init=2, m_cap=m_cap, dt=DT, seed=0, uid=0, weight=1.0 / N)
+    ref = []
+
+    def oracle_steps():
+        for _ in range(STEPS):
+            o.run(1)
+            r = o.last[0]
+            ref.append(({ok: int(getattr(r, ok)) for _, ok in INT_FIELDS}, int(o.m_state[0]),
+                        np.stack([o.vx, o.vy, o.vz], 1).copy()))
+
+    th = threading.Thread(target=oracle_steps)
+    th.start()
     inst = T.Instance(n_particles=N, eps=eps, alpha=0.0, trunc=tr, m_init=2, m_cap=m_cap, dt=DT, seed=0, uid=0,
                       precision=T.FP64, particle_weight=1.0 / N)
     ctx = T.Context([inst], [T.device_particles(vx, vy, vz, precision=T.FP64)])
-    o = orc.Instance(vx, vy, vz, eps=eps, alpha=0.0, trunc=orc.NATURAL if trunc == "natural" else orc.ADAPTIVE,
-                     m_init=2, m_cap=m_cap, dt=DT, seed=0, uid=0, weight=1.0 / N)
-    worst = 0.0
+    gpu = []
     try:
         for s in range(STEPS):
             ctx.step(1)
-            o.run(1)
             got, mom = ctx.read(0), ctx.moments(0)
-            r = o.last[0]
-            for gk, ok in INT_FIELDS:
-                assert int(mom[gk][0]) == int(getattr(r, ok)), f"step {s}: {gk}"
-            assert int(mom["m_state"][0]) == int(o.m_state[0]), f"step {s}: m_state"
-            assert int(mom["status"][0]) == 0
-            ov = np.stack([o.vx, o.vy, o.vz], 1)
-            gv = np.stack([got["vx"], got["vy"], got["vz"]], 1)
-            Tc = ov.var(0).sum() / 3.0
-            err = float(np.abs(gv - ov).max() / math.sqrt(Tc))
-            worst = max(worst, err)
-            assert err <= 1e-12, f"step {s}: max |dv|/sqrt(T) = {err:.3e}"
+            gpu.append((mom, np.stack([got["vx"], got["vy"], got["vz"]], 1)))
     finally:
         ctx.close()
+        th.join()
+    assert len(ref) == STEPS
+    worst = 0.0
+    for s, ((ints, mstate, ov), (mom, gv)) in enumerate(zip(ref, gpu)):
+        for gk, ok in INT_FIELDS:
+            assert int(mom[gk][0]) == ints[ok], f"step {s}: {gk}"
+        assert int(mom["m_state"][0]) == mstate, f"step {s}: m_state"
+        assert int(mom["status"][0]) == 0
+        Tc = ov.var(0).sum() / 3.0
+        err = float(np.abs(gv - ov).max() / math.sqrt(Tc))
+        worst = max(worst, err)
+        assert err <= 1e-12, f"step {s}: max |dv|/sqrt(T) = {err:.3e}"
     say(f"C1 eps {eps} {trunc}: 100 steps, worst |dv|/sqrt(T) {worst:.2e}")
 
 
