@@ -26,6 +26,7 @@ HOMOG, SLAB = 1, 2
 NATURAL, FIXED, ADAPTIVE, ADAPTIVE_REUSE = 0, 1, 2, 3
 WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
 BC_SPECULAR, BC_INFLOW = 0, 1
+MAJ_STEP, MAJ_LEVEL = 0, 1
 
 
 def build() -> str:
@@ -48,6 +49,7 @@ class _Desc(ctypes.Structure):
         ("delta1", ctypes.c_double), ("delta2", ctypes.c_double),
         ("wb", ctypes.c_uint32), ("wb_mmax", ctypes.c_uint32),
         ("bc", ctypes.c_uint32), ("in_left", ctypes.c_double * 3), ("in_right", ctypes.c_double * 3),
+        ("majorant", ctypes.c_uint32),
     ]
 
 
@@ -224,6 +226,7 @@ class Instance:
     in_left: tuple | None = None   # reservoir (rho, u, T) at x = 0, u along +x
     in_right: tuple | None = None  # reservoir (rho, u, T) at x = length
     capacity: int | None = None    # open slab: room for entering particles
+    majorant: int = MAJ_STEP       # MAJ_LEVEL: the VHS bound raised level by level (Remark 4.1)
     step: int = 0
     m_state: np.ndarray | None = None
     last: list | None = None
@@ -261,6 +264,7 @@ class Instance:
         d.delta1, d.delta2 = self.delta1, self.delta2
         d.wb, d.wb_mmax = self.wb, self.wb_mmax
         d.bc = self.bc
+        d.majorant = self.majorant
         if self.in_left is not None:
             d.in_left = (ctypes.c_double * 3)(*self.in_left)
         if self.in_right is not None:

@@ -406,6 +406,7 @@ typedef struct {
     uint32_t m_init, m_cap;
     double delta1, delta2;
     uint32_t wb, wb_mmax; /* tree-shape truncation (reading R15): ORC_WB_* and m_max */
+    uint32_t majorant;    /* ORC_MAJ_STEP, or ORC_MAJ_LEVEL: the bound raised level by level (Remark 4.1) */
 } cell_params;
 
 /* One collision step of one cell, in place on v[0..n). */
@@ -577,7 +578,18 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
             viol = 0;
         }
         uint64_t nf = 0;
+        /* Majorant of the collisions (reading R18).  ORC_MAJ_STEP: the step's bound
+         * sigma(2 dv) for every level.  ORC_MAJ_LEVEL (Remark 4.1: the bound
+         * updated as the collisions change the velocities): the bound of level l
+         * is sigma(2 dv_l), dv_l the largest distance from the cell mean among
+         * the pre-step velocities and the outputs of levels 1..l-1, from which
+         * level l takes its inputs; no pair can then exceed it. */
+        double gl = g, d2seen = dv2;
         for (uint32_t l = 1; l <= T.me; ++l) {
+            if (cp->majorant == ORC_MAJ_LEVEL && l > 1 && cp->alpha != 0.0) {
+                double two_dv = 2.0 * sqrt(d2seen);
+                gl = orc_grid_up(cp->alpha == 1.0 ? two_dv : pow(two_dv, cp->alpha));
+            }
             out[l] = xrealloc(out[l], sizeof(vec3) * (size_t)(2 * T.C[l] + 1));
             for (uint64_t c = 0; c < T.C[l]; ++c) {
                 uint64_t id = T.first[l] + c;
@@ -591,8 +603,15 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
                 double xi1 = unif53(b0[0], b1[0]);
                 double xi2 = unif53(b0[1], b1[1]);
                 double xacc = unif53(b0[2], b1[2]);
-                if (!collide(a, b, xi1, xi2, xacc, cp->alpha, g, &out[l][2 * c], &out[l][2 * c + 1], &viol))
+                if (!collide(a, b, xi1, xi2, xacc, cp->alpha, gl, &out[l][2 * c], &out[l][2 * c + 1], &viol))
                     dummies++;
+            }
+            if (cp->majorant == ORC_MAJ_LEVEL) {
+                for (uint64_t o = 0; o < 2 * T.C[l]; ++o) {
+                    double dx = out[l][o].x - mean.x, dy = out[l][o].y - mean.y, dz = out[l][o].z - mean.z;
+                    double d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 > d2seen) d2seen = d2;
+                }
             }
             /* Finals of level l: the outputs no deeper request took. */
             for (uint64_t o = T.R[l]; o < 2 * T.C[l]; ++o) fin[R0prev + nf++] = out[l][o];
@@ -665,6 +684,7 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         rec->collisions = coll_acc + T.ncoll;
         rec->dummies = dummies;
         rec->violations = viol;
+        rec->g = gl; /* the bound of the last level */
 
         if (!adaptive) break;
 
@@ -860,6 +880,9 @@ int orc_run(const orc_desc* d, uint64_t* n_io, uint64_t cap, double* x, double* 
     if (n > cap) return -1;
     if (d->trunc > ORC_ADAPTIVE_REUSE) return -1;
     if (d->wb > ORC_WB_MEAN || (d->wb != ORC_WB_OFF && (d->trunc >= ORC_ADAPTIVE || d->wb_mmax < 1))) return -1;
+    if (d->majorant > ORC_MAJ_LEVEL ||
+        (d->majorant == ORC_MAJ_LEVEL && (d->wb != ORC_WB_OFF || d->trunc == ORC_ADAPTIVE_REUSE)))
+        return -1;
     double volume = d->geometry == ORC_SLAB ? d->length / (double)nc : d->length;
     double rho_factor = d->weight / volume;
 
@@ -906,7 +929,7 @@ int orc_run(const orc_desc* d, uint64_t* n_io, uint64_t cap, double* x, double* 
             stream_key key = {d->seed, d->uid, c, step};
             cell_params cp = {&key, rho_factor, d->dt, d->eps_cells ? d->eps_cells[c] : d->eps,
                               d->alpha, d->trunc, d->m_init, d->m_cap, d->delta1, d->delta2,
-                              d->wb, d->wb_mmax};
+                              d->wb, d->wb_mmax, d->majorant};
             for (uint64_t i = 0; i < cnt; ++i) {
                 cv[i].x = vx[off + i]; cv[i].y = vy[off + i]; cv[i].z = vz[off + i];
             }

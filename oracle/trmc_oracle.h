@@ -10,6 +10,7 @@ enum { ORC_HOMOG = 1, ORC_SLAB = 2 };
 enum { ORC_NATURAL = 0, ORC_FIXED = 1, ORC_ADAPTIVE = 2, ORC_ADAPTIVE_REUSE = 3 };
 enum { ORC_WB_OFF = 0, ORC_WB_MIN = 1, ORC_WB_MEAN = 2 }; /* tree-shape truncation, Sec. 4.4 */
 enum { ORC_BC_SPECULAR = 0, ORC_BC_INFLOW = 1 };          /* slab ends: walls or reservoirs */
+enum { ORC_MAJ_STEP = 0, ORC_MAJ_LEVEL = 1 };             /* VHS majorant: per step, or raised per level */
 
 typedef struct {
     uint32_t seed, uid;
@@ -27,6 +28,7 @@ typedef struct {
     uint32_t wb_mmax;
     uint32_t bc;         /* ORC_BC_SPECULAR, or ORC_BC_INFLOW: reservoirs at both ends of a slab */
     double in_left[3], in_right[3]; /* reservoir states (rho, u, T); u along +x */
+    uint32_t majorant;   /* ORC_MAJ_STEP, or ORC_MAJ_LEVEL (Remark 4.1; not with reuse or tree shape) */
 } orc_desc;
 
 typedef struct {

@@ -59,6 +59,17 @@ def bimaxwellian(n: int, seed: int = 0, stream: int = 0):
     return v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy()
 
 
+def shell(n: int, radius: float = 1.0, seed: int = 0, stream: int = 0):
+    """Velocities uniform on a sphere of the given radius, shifted to zero mean: every
+    particle starts near the largest distance from the mean, so collisions push some
+    beyond it (a case that exceeds the step's VHS majorant sigma(2 dv))."""
+    g = rng(seed, stream)
+    d = g.standard_normal((n, 3))
+    d *= radius / np.linalg.norm(d, axis=1, keepdims=True)
+    d -= d.mean(0)
+    return d[:, 0].copy(), d[:, 1].copy(), d[:, 2].copy()
+
+
 def maxwellian(n: int, u=(0.0, 0.0, 0.0), T: float = 1.0, seed: int = 0, stream: int = 0):
     g = rng(seed, stream)
     v = g.standard_normal((n, 3)) * math.sqrt(T) + np.asarray(u)[None, :]
