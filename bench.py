@@ -539,6 +539,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one instead of a HIP graph")
     ap.add_argument("--no-fuse", action="store_true",
                     help="one launch per step instead of one launch taking every cell through all timed steps")
+    ap.add_argument("--no-order", action="store_true",
+                    help="launch cells in the order of expected size instead of their measured step time")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of the Poisson request stream")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--speedup-stride", type=int, default=16,
@@ -601,6 +603,7 @@ def main():
     schedule = dict(sorted(schedule.items(), key=lambda kv: int(kv[0][2:])))
     if not args.no_graph:
         ctx.use_graph(True)
+    ctx.order_by_cost(not args.no_order)
     fuse = not args.no_fuse
     log(f"timing {args.steps} steps after {args.warmup} ...")
     wall, avg_ms = time_steps(ctx, args.steps, args.warmup, fuse)
@@ -638,7 +641,8 @@ def main():
                                "eps log-uniform [1e-4, 10], Maxwell/hard-sphere 50/50, adaptive depth m_cap 64, "
                                "dt 0.05",
                    "instances": args.instances, "particles": total, "precision": args.precision,
-                   "schedule": schedule, "graph": not args.no_graph, "fused_steps": fuse},
+                   "schedule": schedule, "graph": not args.no_graph, "fused_steps": fuse,
+                   "launch_order": "size" if args.no_order else "measured step time"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_schedule": json.load(open(TRAFFIC_RECORD))["table"] if traffic else None,

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TRMC_ABI_VERSION 1
+#define TRMC_ABI_VERSION 2
 
 #define TRMC_EINVAL (-22)
 #define TRMC_ENOMEM (-12)
@@ -63,6 +63,13 @@ extern "C" {
 #define TRMC_WB_OFF 0  /* off */
 #define TRMC_WB_MIN 1  /* length 1 + min of the two subtrees' lengths (definition def:2) */
 #define TRMC_WB_MEAN 2 /* length 1 + mean of the two subtrees' lengths (definition def:3) */
+/* VHS majorant of the dummy-collision acceptance (Sec. 4.2, Remark 4.1) */
+#define TRMC_MAJORANT_STEP 0  /* sigma(2 dv) of the step's pre-collision velocities for every level;
+                                 pairs above it collide with probability 1 and are counted */
+#define TRMC_MAJORANT_LEVEL 1 /* raised level by level: level l uses sigma(2 dv_l), dv_l the largest
+                                 distance from the cell mean among the pre-step velocities and the
+                                 outputs of levels below l (no pair can exceed it); not combined with
+                                 TRMC_ADAPTIVE_REUSE or tree-shape truncation */
 /* ends of a slab */
 #define TRMC_BC_SPECULAR 0 /* specular walls (closed slab) */
 #define TRMC_BC_INFLOW 1   /* open slab (Sec. 5.2 stationary shock): each end is a Maxwellian
@@ -99,6 +106,8 @@ typedef struct trmc_desc {
                                which is then the capacity of the arrays); otherwise 0 or n_particles */
     double in_left[3];      /* TRMC_BC_INFLOW: reservoir at x = 0: mass density, mean x velocity, temperature */
     double in_right[3];     /* TRMC_BC_INFLOW: reservoir at x = length (same units; entries move along -x) */
+    uint32_t majorant;      /* TRMC_MAJORANT_STEP or TRMC_MAJORANT_LEVEL (only matters for alpha > 0) */
+    uint32_t reserved;      /* 0 */
 } trmc_desc;
 
 /* Caller-owned device arrays of one instance, SoA, n_particles elements each, of
@@ -133,7 +142,7 @@ typedef struct trmc_cell_moments {
     uint32_t wb_thermalized; /* finals replaced by tree shape (included in thermalized) */
     uint32_t reserved;
     double q;              /* exp(-mu dt / eps) = 1 - tau */
-    double g;              /* majorant (2 dv)^alpha on the 20-bit grid */
+    double g;              /* majorant (2 dv)^alpha on the 20-bit grid (TRMC_MAJORANT_LEVEL: of the last level) */
 } trmc_cell_moments;
 
 #define TRMC_CELL_OVERFLOW 1u /* scratch too small for this cell's trees: cell left unchanged */
@@ -241,6 +250,15 @@ int trmc_use_graph(trmc_ctx* ctx, int on);
  * of a call when it can (see trmc_step); on == 0: one step after another, each
  * its own launches (or graph replay).  Results do not depend on it. */
 int trmc_fuse_steps(trmc_ctx* ctx, int on);
+
+/* Launch order (a scheduling choice, not a passage of the paper).  on != 0 (the
+ * default): before each launch of the whole-cell kernels a device kernel sorts
+ * their work lists (up to 8192 cells each) by the measured wall-clock duration
+ * of every cell's last step, longest first, so that the costliest cells start
+ * first and the launch ends on short ones; cells not yet stepped keep the
+ * order of expected size.  on == 0: the order of expected size.  Results do not
+ * depend on it (every draw is keyed by its cell, not by its position). */
+int trmc_order_by_cost(trmc_ctx* ctx, int on);
 
 /* Wait for the stream and report any asynchronous error. */
 int trmc_sync(trmc_ctx* ctx);

@@ -48,6 +48,10 @@
  *       Maxwellian estimate for the thermalized part, halving (at least 1) below
  *       delta1, keeping between delta1 and delta2, and recomputing from the
  *       pre-step velocities at twice the depth above delta2 (same keyed draws);
+ *       no recompute when it cannot change the result: at m_cap, when the
+ *       split left no remainder, or when continuing the split from the
+ *       remainder would put no particle in any level up to m_cap (the deeper
+ *       trees are then those of depth m);
  *   R9  transport (1-D slab, specular walls) then a stable counting sort by cell,
  *       then the collision step (first-order splitting of Sec. 3.1);
  *   R15 tree-shape truncation (Sec. 4.4, TRMC-WB of Alg. 4.6): a leaf has length
@@ -190,6 +194,19 @@ static uint64_t iround(double y, double u)
 {
     double f = floor(y);
     return (uint64_t)f + (u < y - f ? 1u : 0u);
+}
+
+/* Whether the split of Alg. 4.2, continued past level m with the remainder rem,
+ * would leave levels m+1..m_cap all empty (then a deeper attempt builds the same
+ * trees as depth m).  The draws are those the split at a deeper depth uses. */
+static int split_extension_empty(const stream_key* key, double q, uint64_t rem, uint32_t m, uint32_t m_cap)
+{
+    for (uint32_t k = m + 1; k <= m_cap; ++k) {
+        uint32_t w[4];
+        draw(key, k, TAG_SPLIT, 0, w);
+        if (iround(q * (double)rem, unif53(w[0], w[1])) != 0) return 0;
+    }
+    return 1;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -714,7 +731,10 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         rec->E1 = E1;
         if (E1 < cp->delta1) { *m_state = m / 2 > 1 ? m / 2 : 1; break; }
         if (E1 <= cp->delta2) { *m_state = m; break; }
-        if (m >= cp->m_cap || split_rem == 0) { *m_state = m; break; }
+        if (m >= cp->m_cap || split_rem == 0 || split_extension_empty(key, q, split_rem, m, cp->m_cap)) {
+            *m_state = m;
+            break;
+        }
         if (reuse) {
             for (uint32_t l = 1; l <= T.me; ++l) cprev[l] += T.C[l];
             R0prev = ro.R0;

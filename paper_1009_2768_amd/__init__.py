@@ -17,13 +17,13 @@ import numpy as np
 
 from . import _abi
 from ._abi import (ADAPTIVE, ADAPTIVE_REUSE, FIXED, FP32_MIXED, FP64, HOMOG, NATURAL, PATH_DEFAULT, PATH_GROUP, PATH_TILED,
-                   PATH_WAVE, SCHED_BUCKETS, SLAB1D, WB_MEAN, WB_MIN, WB_OFF, BC_INFLOW, BC_SPECULAR, TrmcError,
-                   check)
+                   PATH_WAVE, SCHED_BUCKETS, SLAB1D, WB_MEAN, WB_MIN, WB_OFF, BC_INFLOW, BC_SPECULAR, MAJORANT_LEVEL,
+                   MAJORANT_STEP, TrmcError, check)
 
 __all__ = ["Instance", "Context", "HOMOG", "SLAB1D", "FP64", "FP32_MIXED", "NATURAL", "FIXED", "ADAPTIVE",
            "ADAPTIVE_REUSE",
            "PATH_DEFAULT", "PATH_GROUP", "PATH_WAVE", "PATH_TILED", "SCHED_BUCKETS", "WB_OFF", "WB_MIN",
-           "WB_MEAN", "BC_SPECULAR", "BC_INFLOW", "TrmcError", "load", "size_bucket", "moments_record_bytes",
+           "WB_MEAN", "BC_SPECULAR", "BC_INFLOW", "MAJORANT_STEP", "MAJORANT_LEVEL", "TrmcError", "load", "size_bucket", "moments_record_bytes",
            "unpack_moments"]
 
 load = _abi.load
@@ -57,6 +57,7 @@ class Instance:
     n_live0: int = 0       # open slab: particles present at admission
     in_left: tuple | None = None   # reservoir (rho, u, T) at x = 0
     in_right: tuple | None = None  # reservoir (rho, u, T) at x = length
+    majorant: int = MAJORANT_STEP  # MAJORANT_LEVEL: VHS bound raised level by level (Remark 4.1)
     _keep: list = field(default_factory=list, repr=False)
 
     def to_c(self) -> _abi.Desc:
@@ -74,6 +75,7 @@ class Instance:
         d.delta1, d.delta2 = self.delta1, self.delta2
         d.wb, d.wb_mmax = self.wb, self.wb_mmax
         d.bc, d.n_live0 = self.bc, self.n_live0
+        d.majorant = self.majorant
         if self.in_left is not None:
             d.in_left = (ctypes.c_double * 3)(*self.in_left)
         if self.in_right is not None:
@@ -212,6 +214,11 @@ class Context:
     def use_graph(self, on: bool = True):
         """Replay one captured HIP graph per step instead of launching each kernel."""
         check(self._lib.trmc_use_graph(self._ctx, 1 if on else 0), "trmc_use_graph")
+
+    def order_by_cost(self, on: bool = True):
+        """Sort the whole-cell work lists by each cell's last measured step time before
+        every launch, longest first (the default); off: the order of expected size."""
+        check(self._lib.trmc_order_by_cost(self._ctx, 1 if on else 0), "trmc_order_by_cost")
 
     def fuse_steps(self, on: bool = True):
         """Let step(n) take homogeneous cells through all n steps in one launch (the default)."""

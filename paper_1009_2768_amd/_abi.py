@@ -11,6 +11,7 @@ FP64, FP32_MIXED = 1, 2
 NATURAL, FIXED, ADAPTIVE, ADAPTIVE_REUSE = 0, 1, 2, 3
 WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
 BC_SPECULAR, BC_INFLOW = 0, 1
+MAJORANT_STEP, MAJORANT_LEVEL = 0, 1
 
 EINVAL, ENOMEM, ENOSPC, EIO, EOVERFLOW = -22, -12, -28, -5, -75
 CELL_OVERFLOW = 1
@@ -19,7 +20,7 @@ EXPORTS = [
     "trmc_abi_version", "trmc_strerror", "trmc_workspace_size", "trmc_ctx_workspace_size", "trmc_init",
     "trmc_step", "trmc_moments", "trmc_state", "trmc_read", "trmc_admit", "trmc_retire", "trmc_sync",
     "trmc_destroy", "trmc_set_schedule", "trmc_get_schedule", "trmc_use_graph", "trmc_count",
-    "trmc_fuse_steps", "trmc_moments_async",
+    "trmc_fuse_steps", "trmc_moments_async", "trmc_order_by_cost",
 ]
 
 SCHED_BUCKETS = 32
@@ -39,6 +40,7 @@ class Desc(ctypes.Structure):
         ("wb", ctypes.c_uint32), ("wb_mmax", ctypes.c_uint32),
         ("bc", ctypes.c_uint32), ("n_live0", ctypes.c_uint32),
         ("in_left", ctypes.c_double * 3), ("in_right", ctypes.c_double * 3),
+        ("majorant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -119,6 +121,8 @@ def load():
     L.trmc_use_graph.restype = i
     L.trmc_fuse_steps.argtypes = [vp, i]
     L.trmc_fuse_steps.restype = i
+    L.trmc_order_by_cost.argtypes = [vp, i]
+    L.trmc_order_by_cost.restype = i
     L.trmc_moments_async.argtypes = [vp, u32, vp, u32]
     L.trmc_moments_async.restype = i
     L.trmc_count.argtypes = [vp, u32, P(ctypes.c_uint64)]

@@ -238,9 +238,12 @@ __device__ __forceinline__ int collide(const Vec3<T>& a, const Vec3<T>& b, T xi1
 struct CellShared {
     double mean[3];
     double Sn, q, g, ur[3], a_th, zbar[3], E1, kept0;
+    double d2max0;  // largest |v - mean|^2 of the pre-step velocities (VHS; else 0)
+    double g_last;  // majorant of the accepted attempt's last level
     double rs[4];  // tree-shape truncation: split remainder's sums of v - mean (3) and |v - mean|^2
     double wbz[9]; // tree-shape truncation: the dropped finals' sums (WbAcc, group totals)
     uint32_t me, split_rem, R0, N0, borrowed, n_th, folds, m, attempts, decision, overflow, wb_th;
+    uint32_t ext_empty;  // the split continued past depth m would leave every level up to m_cap empty
     unsigned long long ncoll, work;
     uint32_t dummies, viol;
 };
@@ -365,6 +368,15 @@ __device__ __forceinline__ Levels levels_at(uint32_t* p, uint32_t stride)
     return L;
 }
 
+// VHS majorant sigma(2 dv) = (2 dv)^alpha rounded up to the 20-bit grid, from the
+// largest squared distance d2 = dv^2 to the cell mean (Sec. 4.2).
+__device__ __forceinline__ double majorant_of(double alpha, double d2)
+{
+#pragma clang fp contract(off)
+    const double two_dv = 2.0 * sqrt(d2);
+    return grid_up20(alpha == 1.0 ? two_dv : pow(two_dv, alpha));
+}
+
 // Majorant, relaxation parameter and depth of the step from the cell's moments
 // (thread 0 of the group): g = (2 dv)^alpha on the 20-bit grid, mu = rho g,
 // q = exp(-mu dt / eps) (Sec. 3.2, Sec. 4.2); m from the truncation mode.
@@ -372,11 +384,9 @@ __device__ __forceinline__ void cell_params(const InstDev* I, uint32_t cell, uin
                                             CellShared& sh)
 {
     double g = 1.0;
-    if (I->alpha != 0.0) {
-#pragma clang fp contract(off)
-        const double two_dv = 2.0 * sqrt(dmax);
-        g = grid_up20(I->alpha == 1.0 ? two_dv : pow(two_dv, I->alpha));
-    }
+    if (I->alpha != 0.0) g = majorant_of(I->alpha, dmax);
+    sh.d2max0 = dmax;
+    sh.g_last = g;
     const double eps = I->eps_cells[cell];
     double xarg;
     {
@@ -402,11 +412,21 @@ __device__ __forceinline__ void cell_params(const InstDev* I, uint32_t cell, uin
     sh.wb_th = 0;
 }
 
+// Depth up to which a split looks ahead for the adaptive decision (0: none).
+__device__ __forceinline__ uint32_t adaptive_look(const InstDev* I)
+{
+    const uint32_t t = uni(I->trunc);
+    return (t == TRUNC_ADAPTIVE || t == TRUNC_ADAPTIVE_REUSE) ? uni(I->m_cap) : 0u;
+}
+
 // a. Split into collision sets (Alg. 4.2) at depth sh.m: wave 0 of the group
 //    draws 64 levels at a time; every lane runs the (uniform) Iround chain.
+//    With look = m_cap (adaptive depth) it also records whether the split,
+//    continued from the remainder, would leave levels m+1..m_cap all empty: a
+//    deeper attempt would then build the same trees, and is not made.
 template <int G>
 __device__ __forceinline__ void split_levels(const Key& key, uint32_t n, double q, const Levels& L, CellShared& sh,
-                                             uint32_t tid)
+                                             uint32_t tid, uint32_t look = 0)
 {
     const uint32_t lane = tid & 63u, wave = tid >> 6;
     if (wave == 0) {
@@ -428,6 +448,28 @@ __device__ __forceinline__ void split_levels(const Key& key, uint32_t n, double 
             if (lane == 0) L.N[k] = Nk;
             rem -= Nk;
         }
+        uint32_t ext_empty = 1;
+        if (look > m && rem > 0) {
+            double y;
+            {
+#pragma clang fp contract(off)
+                y = q * (double)rem;  // Iround's argument at every deeper level while they stay empty
+            }
+            if (y >= 1.0) {
+                ext_empty = 0;
+            } else {
+                // level k gets a particle iff its uniform is below y (floor(y) = 0)
+                for (uint32_t kb = m + 1u; kb <= look && ext_empty; kb += 64u) {
+                    const uint32_t kk = kb + lane;
+                    bool hit = false;
+                    if (kk <= look) {
+                        const uint4 ww = draw(key, kk, TAG_SPLIT, 0);
+                        hit = u53(ww.x, ww.y) < y;
+                    }
+                    if (__ballot(hit) != 0ull) ext_empty = 0;
+                }
+            }
+        }
         if (lane == 0) {
             L.N[k + 1] = rem;
             sh.me = k;
@@ -435,6 +477,7 @@ __device__ __forceinline__ void split_levels(const Key& key, uint32_t n, double 
             sh.N0 = N0;
             sh.folds = 0;
             sh.attempts += 1;
+            sh.ext_empty = ext_empty;
         }
     }
     gsync_lds<G>();
@@ -463,8 +506,17 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
     const uint32_t lane = tid & 63u, wave = tid >> 6;
     const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64u - lane));
     unsigned long long ncoll = 0;
+    // Depth of the trees: the split's depth when its trees fit in the cell;
+    // otherwise the largest depth whose trees fit, found by bisection.  The
+    // leaves a depth needs never decrease with the depth (the levels below it
+    // and their keyed choices are the same, and every level's collision count
+    // grows with the requests it receives), so this is the depth at which the
+    // fold rule's level-by-level descent stops, in O(log depth) builds.
+    const uint32_t me_split = uni(sh.me);
+    uint32_t lo = REUSE ? (mfloor < me_split ? mfloor : me_split) : 0u;  // a depth that fits
+    uint32_t hi = me_split;  // a depth that does not fit, once the first build has failed
+    uint32_t me = me_split;  // depth of the current build
     for (;;) {
-        const uint32_t me = uni(sh.me);
         for (uint32_t l = tid; l <= me; l += G) L.run[l] = 0;
         gsync_lds<G>();
         ncoll = 0;
@@ -596,11 +648,20 @@ __device__ __forceinline__ unsigned long long build_trees(const Key& key, uint32
         }
         if (tid == 0) sh.R0 = L.run[0];
         gsync_lds<G>();
-        if (REUSE ? (r0prev + sh.R0 <= n || me <= mfloor) : sh.R0 <= n) break;
+        const bool fits = REUSE ? (r0prev + uni(sh.R0) <= n || me <= mfloor) : uni(sh.R0) <= n;
+        if (fits) lo = me;
+        else hi = me;
+        if (fits && (me == me_split || hi - lo <= 1u)) break;  // the schedule of depth lo is built
+        me = hi - lo <= 1u ? lo : lo + (hi - lo) / 2u;       // bisect, or rebuild the final depth
+    }
+    if (me < me_split) {
+        // the levels above me are folded into the remainder
         if (tid == 0) {
-            L.N[me] += L.N[me + 1];
-            sh.me = me - 1u;
-            sh.folds += 1;
+            uint32_t rem = 0;
+            for (uint32_t l = me + 1u; l <= me_split + 1u; ++l) rem += L.N[l];
+            L.N[me + 1u] = rem;
+            sh.me = me;
+            sh.folds += me_split - me;
         }
         gsync_lds<G>();
     }
@@ -711,6 +772,15 @@ __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, 
 #endif
 constexpr int kBU = TRMC_BOTTOM_UP_BATCH;  // collisions per thread per batch in bottom_up
 
+// Majorant raised level by level (Remark 4.1): the bound of level l + 1 is the
+// majorant of the largest distance to the cell mean among the pre-step
+// velocities (d2seen starts at their largest squared distance) and the outputs
+// of levels 1..l.  red: group reduction scratch; g: the bound of the next level.
+struct DynMajorant {
+    double* red;
+    double alpha, d2seen, g;
+};
+
 // Tree-shape truncation: the finals longer than m_max, summed where they are
 // made.  z: the normals of their slots (sum of the 3 components, sum of |z|^2);
 // d: their values less the cell mean (3 sums, sum of |v - mean|^2); cnt: count.
@@ -725,7 +795,7 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                                           unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
                                           uint32_t& dummies, uint32_t& viol, double& sfin, uint32_t wbk = 0,
                                           const uint32_t* coff = nullptr, uint32_t r0prev = 0,
-                                          WbAcc* wba = nullptr, T wbmax = T(0))
+                                          WbAcc* wba = nullptr, T wbmax = T(0), DynMajorant* dm = nullptr)
 {
     const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
     // tree-shape truncation: a dropped final's slot is the permutation of its
@@ -747,6 +817,7 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
         const uint32_t fst = (uint32_t)above;
         const uint32_t oo = uni(L.outoff[l]);
         [[maybe_unused]] const uint32_t c_off = REUSE ? uni(coff[l]) : 0u;
+        double lvmax = 0.0;  // dynamic majorant: largest |output - mean|^2 of this level (this thread)
         // kBU collisions per thread: every index and input load of the batch
         // is issued before the first collision is computed
         for (uint32_t c0 = tid; c0 < Cl; c0 += G * kBU) {
@@ -803,6 +874,15 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                 Draws<T>::coll(key, l, REUSE ? c_off + c : c, xi1, xi2, xacc);
                 Vec3<T> out[2];
                 if (!collide<T>(a[k], b[k], xi1, xi2, xacc, alpha, gT, out[0], out[1], viol)) dummies++;
+                if (dm) {
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const double ex = (double)out[e].x - mx, ey = (double)out[e].y - sh.mean[1],
+                                     ez = (double)out[e].z - sh.mean[2];
+                        const double d2 = ex * ex + ey * ey + ez * ez;
+                        lvmax = d2 > lvmax ? d2 : lvmax;
+                    }
+                }
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const uint32_t o = 2u * c + (uint32_t)e;
@@ -835,6 +915,13 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
             }
         }
         fp += 2u * Cl - Rl;
+        if (dm) {
+            // the bound of the next level (every thread computes the same value)
+            const double lm = gmax<G>(lvmax, dm->red);
+            dm->d2seen = lm > dm->d2seen ? lm : dm->d2seen;
+            dm->g = majorant_of(dm->alpha, dm->d2seen);
+            gT = (T)dm->g;
+        }
         gsync<G>();
     }
 }
@@ -874,7 +961,7 @@ __device__ __forceinline__ void decide(InstDev* I, uint32_t cell, uint32_t n, co
             sh.E1 = E1;
             if (E1 < I->delta1) I->m_state[cell] = (m / 2u > 1u) ? m / 2u : 1u;
             else if (E1 <= I->delta2) I->m_state[cell] = m;
-            else if (m >= I->m_cap || sh.split_rem == 0u) I->m_state[cell] = m;
+            else if (m >= I->m_cap || sh.split_rem == 0u || sh.ext_empty) I->m_state[cell] = m;
             else {
                 sh.m = (2u * m < I->m_cap) ? 2u * m : I->m_cap;
                 decision = 0;
@@ -939,9 +1026,17 @@ __device__ __forceinline__ void attempt_sums(gptr<const T> vx, gptr<const T> vy,
     for (int q = 0; q < 6; ++q) all[q] = v[q];
 }
 
-__device__ __forceinline__ void write_stats(CellStats* st, uint32_t n, const CellShared& sh)
+// Wall-clock ticks since t_begin (100 MHz constant-rate counter), saturated to 32 bits.
+__device__ __forceinline__ uint32_t elapsed_ticks(uint64_t t_begin)
+{
+    const uint64_t d = wall_clock64() - t_begin;
+    return d > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d;
+}
+
+__device__ __forceinline__ void write_stats(CellStats* st, uint32_t n, const CellShared& sh, uint32_t ticks = 0)
 {
     CellStats s{};
+    s.ticks = ticks;
     s.n = n;
     s.N0 = sh.N0;
     s.m_eff = sh.me;
@@ -958,7 +1053,7 @@ __device__ __forceinline__ void write_stats(CellStats* st, uint32_t n, const Cel
     s.violations = sh.viol;
     s.work_collisions = sh.work;
     s.q = sh.q;
-    s.g = sh.g;
+    s.g = sh.g_last;
     s.E1 = sh.E1;
     *st = s;
 }

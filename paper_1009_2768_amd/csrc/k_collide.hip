@@ -26,6 +26,8 @@ namespace trmc {
 // Profiling build only: per-phase wall-clock totals by cell-size class.
 __device__ unsigned long long g_phase[4][12];
 __device__ unsigned long long g_maxcell[12];
+// per workgroup of a launch (at most 16384): first start and last end of its groups' steps
+__device__ unsigned long long g_span[16384][2];
 #define TRMC_PHASE_BEGIN() unsigned long long ph_t = wall_clock64(), ph_acc[10] = {0,0,0,0,0,0,0,0,0,0}
 #define TRMC_PHASE(k)                                   \
     do {                                                \
@@ -76,7 +78,7 @@ constexpr int kUnroll = TRMC_SLOT_UNROLL;  // slots per thread per batch in the 
 // One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
 // it once per step, and inlined into their step loops the compiler keeps
 // per-step values live across the whole loop and spills them.
-template <typename T, int NT, int G, bool WB = false, bool REUSE = false>
+template <typename T, int NT, int G, bool WB = false, bool REUSE = false, bool DYN = false>
 __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restrict__ work, uint32_t n_work, uint32_t blk,
                                               uint32_t lv_stride, uint32_t soff)
 {
@@ -101,6 +103,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     const gptr<T> vz = as_global(uni(reinterpret_cast<T*>(I->vz[buf]) + off));
     CellStats* st = I->stats + cell;
     const Key key = uni(Key{I->seed, I->uid, cell, I->step + soff});  // step soff of this launch
+    const uint64_t t_begin = wall_clock64();  // the step's duration orders the next launch
 
 #ifndef TRMC_PRIO_CELL
 #define TRMC_PRIO_CELL 16384u
@@ -249,7 +252,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     }
     for (;;) {
         [[maybe_unused]] const uint32_t m_att = REUSE ? uni(sh.m) : 0u;
-        split_levels<G>(key, n, sh.q, L, sh, tid);
+        split_levels<G>(key, n, sh.q, L, sh, tid, adaptive_look(I));
         if constexpr (REUSE) {
             if (mprev) {
                 const uint32_t me0 = uni(sh.me);
@@ -297,9 +300,13 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
         [[maybe_unused]] WbAcc wba{};
+        // the majorant raised level by level (Remark 4.1), from the step's bound
+        DynMajorant dmj{gl.red, I->alpha, sh.d2max0, sh.g};
+        const bool dyn = DYN && I->alpha != 0.0;
         bottom_up<T, G, false, WB, REUSE>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol,
                                           sfin, WB ? uni(I->wb) : 0u, coff, r0prev, &wba,
-                                          WB ? (T)uni(I->wb_mmax) : T(0));
+                                          WB ? (T)uni(I->wb_mmax) : T(0), dyn ? &dmj : nullptr);
+        if (tid == 0) sh.g_last = dmj.g;
         if constexpr (WB) {
             double v[9] = {wba.z[0], wba.z[1], wba.z[2], wba.z[3], wba.d[0], wba.d[1], wba.d[2], wba.d[3], wba.cnt};
             gsum<G, 9>(v, gl.red);
@@ -357,6 +364,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
             s.n = n;
             s.status = CELL_OVERFLOW;
             s.m_used = sh.m;
+            s.ticks = elapsed_ticks(t_begin);
             *st = s;
             atomicOr(I->error, CELL_OVERFLOW);
         }
@@ -500,32 +508,68 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     }
     TRMC_PHASE(7);
     TRMC_PHASE_END(n);
-    if (tid == 0) write_stats(st, n, sh);
+    if (tid == 0) write_stats(st, n, sh, elapsed_ticks(t_begin));
 }
 
-// Cells of the workgroup-per-cell list occupy the first n_big workgroups, cells
-// of the wave-per-cell list (eight per workgroup) the rest.  Each group takes
-// its cell through nsteps consecutive steps (nsteps > 1 only for homogeneous
-// instances, whose cells depend on nothing but themselves); the group's
-// barrier orders one step's stores before the next step's loads.
+// Groups of eight wave-per-cell cells occupy the first workgroups, cells of the
+// workgroup-per-cell list the rest: the dispatcher starts workgroups in index
+// order, and the few small-cell groups, whose deep trees make their waves run
+// long, start with the longest big cells instead of at the end of the launch.
+// Each group takes its cell through nsteps consecutive steps (nsteps > 1 only
+// for homogeneous instances, whose cells depend on nothing but themselves); the
+// group's barrier orders one step's stores before the next step's loads.  At
+// the end, the cell's wall-clock time over the launch replaces the last step's
+// in its counters: the cost by which the next launch is ordered.
 template <typename T, bool REUSE = false>
 __device__ __forceinline__ void collide_entry(const CellRef* __restrict__ big, uint32_t n_big, uint32_t lv_big,
                                               const CellRef* __restrict__ small, uint32_t n_small, uint32_t lv_small,
                                               uint32_t nsteps)
 {
+    const uint32_t small_blocks = (n_small + kSmallPerBlock - 1u) / kSmallPerBlock;
+    const uint64_t t_launch = wall_clock64();
+#ifdef TRMC_PHASE_TIMING
+    if (threadIdx.x == 0 && blockIdx.x < 16384u) g_span[blockIdx.x][0] = wall_clock64();
+#endif
     for (uint32_t s = 0; s < nsteps; ++s) {
         // an opaque copy of the block index: the cell's loads are made again in
         // every step instead of being kept live across the steps
         uint32_t b = blockIdx.x;
         asm volatile("" : "+s"(b));
-        if (b < n_big) {
-            collide_cells<T, kCollideThreads, kCollideThreads, false, REUSE>(big, n_big, b, lv_big, s);
+        // cells of instances with the majorant raised level by level take their
+        // own instance of the step (the plain one keeps its register budget)
+        if (b >= small_blocks) {
+            const uint32_t bb = b - small_blocks;
+            if (!REUSE && uni(big[bb].inst->majorant) == MAJ_LEVEL)
+                collide_cells<T, kCollideThreads, kCollideThreads, false, false, true>(big, n_big, bb, lv_big, s);
+            else
+                collide_cells<T, kCollideThreads, kCollideThreads, false, REUSE>(big, n_big, bb, lv_big, s);
             gsync<kCollideThreads>();
         } else {
-            collide_cells<T, kCollideThreads, 64, false, REUSE>(small, n_small, b - n_big, lv_small, s);
+            const uint32_t wi = b * kSmallPerBlock + uni((uint32_t)(threadIdx.x / 64));
+            if (!REUSE && wi < n_small && uni(small[wi].inst->majorant) == MAJ_LEVEL)
+                collide_cells<T, kCollideThreads, 64, false, false, true>(small, n_small, b, lv_small, s);
+            else
+                collide_cells<T, kCollideThreads, 64, false, REUSE>(small, n_small, b, lv_small, s);
             gsync<64>();
         }
     }
+    // the cell's time over the whole launch (lane 0 of its group)
+    {
+        uint32_t b = blockIdx.x;
+        asm volatile("" : "+s"(b));
+        const CellRef* r = nullptr;
+        if (b >= small_blocks) {
+            if (threadIdx.x == 0 && b - small_blocks < n_big) r = &big[b - small_blocks];
+        } else {
+            const uint32_t wi = b * kSmallPerBlock + (uint32_t)(threadIdx.x / 64);
+            if ((threadIdx.x & 63u) == 0 && wi < n_small) r = &small[wi];
+        }
+        if (r) r->inst->stats[r->cell].ticks = elapsed_ticks(t_launch);
+    }
+#ifdef TRMC_PHASE_TIMING
+    __syncthreads();
+    if (threadIdx.x == 0 && blockIdx.x < 16384u) g_span[blockIdx.x][1] = wall_clock64();
+#endif
 }
 
 // The per-cell chains are latency bound, so resident waves matter: the FP32
@@ -620,11 +664,74 @@ k_collide<double>(const CellRef* __restrict__ big, uint32_t n_big,
     collide_entry<double>(big, n_big, lv_big, small, n_small, lv_small, nsteps);
 }
 
+// Launch order of the whole-cell kernels: a work list sorted by the measured
+// duration of each cell's last step, longest first, ties in their previous
+// order (longest-processing-time-first: the dispatcher starts workgroups in
+// index order as compute units free up, so the costliest cells start first and
+// the launch ends on short ones).  Block b sorts list b in place, if it holds
+// 2 to kOrderMax items.  The order decides when a cell runs, never what it
+// computes.  Cells not yet stepped have duration 0 and keep the size order.
+constexpr uint32_t kOrderMax = 8192;
+constexpr uint32_t kOrderThreads = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void k_order(CellRef* __restrict__ l0, uint32_t n0,
+                                                          CellRef* __restrict__ l1, uint32_t n1)
+{
+    __shared__ uint64_t key[kOrderMax];
+    CellRef* __restrict__ list = blockIdx.x == 0 ? l0 : l1;
+    const uint32_t n = blockIdx.x == 0 ? n0 : n1;
+    if (n < 2u || n > kOrderMax) return;
+    uint32_t P = 2;
+    while (P < n) P <<= 1;
+    // key: (longest first, then previous position), padded with the largest key
+    for (uint32_t i = threadIdx.x; i < P; i += kOrderThreads) {
+        uint64_t k = ~0ull;
+        if (i < n) {
+            const CellRef r = list[i];
+            const uint32_t t = r.inst->stats[r.cell].ticks;
+            k = ((uint64_t)(0xFFFFFFFFu - t) << 32) | i;
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    // bitonic sort, ascending
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P; i += kOrderThreads) {
+                const uint32_t p = i ^ j;
+                if (p > i) {
+                    const uint64_t a = key[i], b = key[p];
+                    if ((a > b) == ((i & k) == 0u)) {
+                        key[i] = b;
+                        key[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // every item's new entry is read before any is written
+    constexpr int Q = kOrderMax / kOrderThreads;
+    CellRef tmp[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t i = threadIdx.x + (uint32_t)q * kOrderThreads;
+        if (i < n) tmp[q] = list[(uint32_t)key[i]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t i = threadIdx.x + (uint32_t)q * kOrderThreads;
+        if (i < n) list[i] = tmp[q];
+    }
+}
+
 #ifdef TRMC_PHASE_TIMING
-extern "C" int trmc_debug_phase_totals(unsigned long long* out /* 60 */, int reset)
+extern "C" int trmc_debug_phase_totals(unsigned long long* out /* 60 + 2 * 16384 */, int reset)
 {
     if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return -5;
     if (hipMemcpyFromSymbol(out + 48, HIP_SYMBOL(g_maxcell), sizeof(g_maxcell)) != hipSuccess) return -5;
+    if (hipMemcpyFromSymbol(out + 60, HIP_SYMBOL(g_span), sizeof(g_span)) != hipSuccess) return -5;
     if (reset) {
         static const unsigned long long zero[4][12] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), zero, sizeof(zero)) != hipSuccess) return -5;

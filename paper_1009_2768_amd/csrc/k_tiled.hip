@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kTT) void k_big_split(const CellRef* __restrict__ b
         sh.overflow = n < 2 ? 1u : 0u;  // cells of fewer than 2 particles are skipped
     }
     gsync<64>();
-    if (n >= 2) split_levels<64>(key, n, sh.q, L, sh, lane);
+    if (n >= 2) split_levels<64>(key, n, sh.q, L, sh, lane, adaptive_look(I));
     // expected collisions of the trees: a level-k sample costs H_k / 2 of them
     double est = 0.0, Hk = 0.0;
     if (n >= 2)
@@ -367,7 +367,12 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
         attempt_sums<T, G>(vx, vy, vz, M.fwd, I->bsum, n, kept_end, leaf_end, mx, my, mz, tid, gl.red, all);
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
-        bottom_up<T, G, true>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin);
+        // the majorant raised level by level (Remark 4.1), from the step's bound
+        DynMajorant dmj{gl.red, I->alpha, sh.d2max0, sh.g};
+        const bool dyn = uni(I->majorant) == MAJ_LEVEL && I->alpha != 0.0;
+        bottom_up<T, G, true>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin, 0u,
+                              nullptr, 0u, nullptr, T(0), dyn ? &dmj : nullptr);
+        if (tid == 0) sh.g_last = dmj.g;
         double fs[1] = {sfin};
         gsum<G, 1>(fs, gl.red);
         const uint32_t td = gsum_u32<G>(dummies, gl.redu);
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
         gsync<G>();
         if (sh.decision) break;
         // redo at depth sh.m
-        split_levels<G>(key, n, sh.q, L, sh, tid);
+        split_levels<G>(key, n, sh.q, L, sh, tid, adaptive_look(I));
         ncoll = build_trees<G>(key, n, M.cap, L, gl, sh, M.jarr, M.rA, M.rB, tid);
         if (sh.overflow || !level_offsets<G>(n, ncoll, M.ocap, L, sh, tid)) break;
     }

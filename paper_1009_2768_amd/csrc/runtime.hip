@@ -50,6 +50,8 @@ __global__ void k_tile_zsum(const CellRef*, const uint32_t*, uint32_t);
 template <typename T>
 __global__ void k_tile_write(const CellRef*, const uint32_t*, uint32_t);
 __global__ void k_advance(InstDev* const*, uint32_t, uint32_t);
+__global__ void k_order(CellRef*, uint32_t, CellRef*, uint32_t);
+constexpr uint32_t kOrderThreads = 1024;
 }  // namespace trmc
 
 using namespace trmc;
@@ -140,6 +142,9 @@ int validate(const trmc_desc* d)
         return TRMC_EINVAL;
     }
     if (d->wb != TRMC_WB_OFF && (d->trunc >= TRMC_ADAPTIVE || d->wb_mmax < 1)) return TRMC_EINVAL;
+    if (d->majorant > TRMC_MAJORANT_LEVEL || d->reserved != 0) return TRMC_EINVAL;
+    if (d->majorant == TRMC_MAJORANT_LEVEL && (d->wb != TRMC_WB_OFF || d->trunc == TRMC_ADAPTIVE_REUSE))
+        return TRMC_EINVAL;
     if (d->m_state0) {
         for (uint32_t c = 0; c < nc; ++c)
             if (d->m_state0[c] < 1 || d->m_state0[c] > d->m_cap) return TRMC_EINVAL;
@@ -196,6 +201,9 @@ struct trmc_ctx {
     // and possible (every active instance homogeneous, no cell on the tiled path)
     bool fuse = true;
     bool fusable = false;
+    // whole-cell work lists re-sorted on the device before each launch by the
+    // duration of every cell's last step, longest first (trmc_order_by_cost)
+    bool order = true;
     hipStream_t cap_stream = nullptr;  // stream the step is captured on
     // the tile pipeline of large homogeneous cells runs on a second stream, beside
     // the slab sort and the whole-cell kernels (they touch different cells)
@@ -451,6 +459,7 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     h.n_tiles = L.n_tiles;
     h.wb = d->wb;
     h.wb_mmax = d->wb_mmax;
+    h.majorant = d->majorant;
     h.length = d->length;
     h.dt = d->dt;
     const double volume = d->geometry == TRMC_SLAB1D ? d->length / (double)nc : d->length;
@@ -559,6 +568,8 @@ template <typename T>
 int launch_whole(trmc_ctx* c, int k, uint32_t nsteps = 1)
 {
     const uint32_t nb = c->n_work[k][0], ns = c->n_work[k][1];
+    if (c->order && (nb > 1 || ns > 1))
+        hipLaunchKernelGGL(k_order, dim3(2), dim3(kOrderThreads), 0, c->stream, c->work[k][0], nb, c->work[k][1], ns);
     if (nb + ns) {
         const uint32_t small_blocks = (ns + kSmallPerBlock - 1) / kSmallPerBlock;
         const size_t lds = std::max(sizeof(uint32_t) * 5 * c->lv_stride[k][0],
@@ -571,6 +582,8 @@ int launch_whole(trmc_ctx* c, int k, uint32_t nsteps = 1)
                            c->stream, c->work[k][3], nw, c->lv_stride[k][3], nsteps);
     }
     const uint32_t rb = c->n_work[k][4], rs = c->n_work[k][5];
+    if (c->order && (rb > 1 || rs > 1))
+        hipLaunchKernelGGL(k_order, dim3(2), dim3(kOrderThreads), 0, c->stream, c->work[k][4], rb, c->work[k][5], rs);
     if (rb + rs) {
         const uint32_t small_blocks = (rs + kSmallPerBlock - 1) / kSmallPerBlock;
         const size_t lds = std::max(sizeof(uint32_t) * 6 * c->lv_stride[k][4],
@@ -874,6 +887,18 @@ int trmc_fuse_steps(trmc_ctx* c, int on)
     if (!c) return TRMC_EINVAL;
     if (c->sticky) return c->sticky;
     c->fuse = on != 0;
+    return 0;
+}
+
+int trmc_order_by_cost(trmc_ctx* c, int on)
+{
+    if (!c) return TRMC_EINVAL;
+    if (c->sticky) return c->sticky;
+    if (c->order != (on != 0)) {
+        c->order = on != 0;
+        c->graph_dirty = true;
+        if (!c->order) return rebuild_tables(c);  // back to the size order
+    }
     return 0;
 }
 

@@ -11,6 +11,7 @@ enum : uint32_t { PREC_FP64 = 1, PREC_FP32 = 2 };
 enum : uint32_t { TRUNC_NATURAL = 0, TRUNC_FIXED = 1, TRUNC_ADAPTIVE = 2, TRUNC_ADAPTIVE_REUSE = 3 };
 enum : uint32_t { WB_OFF = 0, WB_MIN = 1, WB_MEAN = 2 };  // tree-shape truncation (Sec. 4.4)
 enum : uint32_t { CELL_OVERFLOW = 1u, INJECT_FULL = 2u };  // context error word bits
+enum : uint32_t { MAJ_STEP = 0, MAJ_LEVEL = 1 };  // VHS majorant (Sec. 4.2, Remark 4.1)
 
 constexpr uint32_t kMaxDepth = 2048;     // largest m_cap accepted
 constexpr uint32_t kMaxSlabCells = 12288;  // LDS histogram of the sort
@@ -45,7 +46,8 @@ constexpr uint32_t kSmallDepth = 256;  // ... if their m_cap is at most this
 
 // Counters of one cell's last collision step.
 struct CellStats {
-    uint32_t n, N0, m_eff, m_used, attempts, R0, n_th, borrowed, folds, status, wb_th, pad;
+    uint32_t n, N0, m_eff, m_used, attempts, R0, n_th, borrowed, folds, status, wb_th;
+    uint32_t ticks;  // wall-clock duration of the cell's step (100 MHz counter): its cost in the launch order
     unsigned long long collisions, dummies, violations, work_collisions;
     double q, g, E1;
 };
@@ -67,7 +69,7 @@ struct InstDev {
     uint32_t bc;            // slab ends: 0 specular walls, 1 reservoirs (open slab)
     uint32_t n_live;        // particles in the slab (open slab: changes every step; else n)
     uint32_t n_next;        // open slab: particles left after this step's transport
-    uint32_t pad1;
+    uint32_t majorant;      // MAJ_STEP, or MAJ_LEVEL: the VHS bound raised level by level
     double in_sig[2], in_a[2], in_lam[2];  // reservoirs: sqrt(T), inward drift / sqrt(T), mean entries per step
     double length, dt, rho_factor, alpha, delta1, delta2, inv_dx;
     const double* eps_cells;  // [n_cells]

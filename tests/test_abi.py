@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(T):
 
 def test_abi_version_and_strerror(T):
     L = T.load()
-    assert L.trmc_abi_version() == 1
+    assert L.trmc_abi_version() == 2
     for code in (0, -22, -12, -28, -5, -75):
         assert len(L.trmc_strerror(code)) > 0
 
@@ -75,6 +75,9 @@ def _ws(T, **kw):
     dict(n_particles=100, trunc=1, wb=3), dict(n_particles=100, trunc=1, wb=1, wb_mmax=0),
     dict(n_particles=100, trunc=2, wb=2, wb_mmax=5), dict(n_particles=100, trunc=3, wb=1, wb_mmax=5),
     dict(n_particles=100, trunc=4), dict(n_particles=100, trunc=3, delta1=0.02, delta2=0.01),
+    # majorant raised level by level: unknown mode, with reuse, with tree-shape truncation
+    dict(n_particles=100, majorant=2), dict(n_particles=100, trunc=3, majorant=1),
+    dict(n_particles=100, trunc=1, wb=1, wb_mmax=2, majorant=1),
 ])
 def test_invalid_descriptors_rejected(T, bad):
     rc, _ = _ws(T, **bad)
@@ -82,7 +85,8 @@ def test_invalid_descriptors_rejected(T, bad):
 
 
 @pytest.mark.parametrize("ok", [dict(n_particles=100, trunc=1, wb=1, wb_mmax=1),
-                                dict(n_particles=100, trunc=0, wb=2, wb_mmax=64)])
+                                dict(n_particles=100, trunc=0, wb=2, wb_mmax=64),
+                                dict(n_particles=100, trunc=2, alpha=1.0, majorant=1)])
 def test_tree_shape_truncation_descriptors_accepted(T, ok):
     rc, n = _ws(T, **ok)
     assert rc == 0 and n > 0

@@ -1,0 +1,127 @@
+"""GPU: the VHS majorant raised level by level (Remark 4.1) through the C ABI,
+against the FP64 oracle: integers exact (collisions, dummies, no violations),
+velocities within 1e-12 of the thermal speed, the recorded bound equal; on the
+workgroup, wave and tile paths; beside plain instances; FP32 conserves and has
+no violations."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trmc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm GPU"
+    import paper_1009_2768_amd as T
+    T.load()
+    return T
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def case(T, n, eps, trunc, m, uid, precision, majorant):
+    v = W.shell(n, seed=41, stream=uid)
+    inst = T.Instance(n_particles=n, eps=eps, alpha=1.0, trunc=trunc, m_init=m, m_cap=64, uid=uid, seed=0, dt=0.05,
+                      precision=precision, particle_weight=1.0 / n, majorant=majorant)
+    return inst, v
+
+
+def oracle_run(orc, inst, v, steps):
+    o = orc.Instance(*v, eps=inst.eps, alpha=inst.alpha, trunc=inst.trunc, m_init=inst.m_init, m_cap=inst.m_cap,
+                     uid=inst.uid, seed=inst.seed, dt=inst.dt, weight=inst.particle_weight,
+                     majorant=inst.majorant)
+    o.run(steps)
+    return o
+
+
+@pytest.mark.parametrize("path", ["group", "wave", "tiled"])
+@pytest.mark.parametrize("trunc", ["fixed", "adaptive"])
+def test_level_majorant_fp64_matches_oracle(trmc, orc, path, trunc):
+    T = trmc
+    say("level majorant fp64", path, trunc)
+    tr = T.FIXED if trunc == "fixed" else T.ADAPTIVE
+    insts, vs = [], []
+    for k, (n, eps) in enumerate([(3000, 0.05), (1200, 0.02), (9000, 0.1)]):
+        inst, v = case(T, n, eps, tr, 24, 10 + k, T.FP64, T.MAJORANT_LEVEL)
+        insts.append(inst)
+        vs.append(v)
+    parts = [T.device_particles(*v, precision=T.FP64) for v in vs]
+    ctx = T.Context(insts, parts)
+    p = {"group": T.PATH_GROUP, "wave": T.PATH_WAVE, "tiled": T.PATH_TILED}[path]
+    ctx.set_schedule([p] * T.SCHED_BUCKETS)
+    ctx.step(1)
+    got = [(ctx.read(k), ctx.moments(k)) for k in range(len(insts))]
+    ctx.close()
+    viol_fixed = 0
+    for inst, v, (g, mom) in zip(insts, vs, got):
+        o = oracle_run(orc, inst, v, 1)
+        r = o.last[0]
+        for gk, ok in (("collisions", "collisions"), ("dummies", "dummies"), ("violations", "violations"),
+                       ("thermalized", "n_th"), ("R0", "R0"), ("m_used", "m_used"), ("attempts", "attempts")):
+            assert int(mom[gk][0]) == int(getattr(r, ok)), (inst.n_particles, gk)
+        assert int(mom["violations"][0]) == 0
+        assert float(mom["g"][0]) == r.g
+        ov = np.stack([o.vx, o.vy, o.vz], 1)
+        gv = np.stack([g["vx"], g["vy"], g["vz"]], 1)
+        err = float(np.abs(gv - ov).max() / math.sqrt(ov.var(0).sum() / 3.0))
+        assert err <= 1e-12, (inst.n_particles, err)
+        plain = orc.Instance(*v, eps=inst.eps, alpha=1.0, trunc=inst.trunc, m_init=24, m_cap=64, uid=inst.uid,
+                             dt=0.05, weight=inst.particle_weight)
+        plain.run(1)
+        viol_fixed += int(plain.last[0].violations)
+    assert viol_fixed > 0  # the same cases exceed the step's bound without the update
+
+
+def test_level_majorant_beside_plain_equals_alone(trmc):
+    T = trmc
+    say("level majorant beside plain instances")
+    a, va = case(T, 4000, 0.05, T.FIXED, 16, 21, T.FP64, T.MAJORANT_LEVEL)
+    b, vb = case(T, 4000, 0.05, T.FIXED, 16, 22, T.FP64, T.MAJORANT_STEP)
+    c, vc = case(T, 300, 0.05, T.FIXED, 16, 23, T.FP64, T.MAJORANT_LEVEL)
+
+    def run(insts, vs):
+        ctx = T.Context(insts, [T.device_particles(*v, precision=T.FP64) for v in vs])
+        ctx.step(2)
+        out = [ctx.read(k) for k in range(len(insts))]
+        ctx.close()
+        return out
+
+    mix = run([a, b, c], [va, vb, vc])
+    for k, (i, v) in enumerate(((a, va), (b, vb), (c, vc))):
+        alone = run([i], [v])[0]
+        for key in ("vx", "vy", "vz"):
+            assert np.array_equal(mix[k][key], alone[key]), (k, key)
+
+
+def test_level_majorant_fp32_conserves_without_violations(trmc):
+    T = trmc
+    say("level majorant fp32")
+    inst, v = case(T, 20000, 0.05, T.ADAPTIVE, 4, 31, T.FP32_MIXED, T.MAJORANT_LEVEL)
+    ctx = T.Context([inst], [T.device_particles(*v, precision=T.FP32_MIXED)])
+    v0 = np.stack(v).astype(np.float32).astype(np.float64)
+    for _ in range(3):
+        ctx.step(1)
+        mom = ctx.moments(0)
+        assert int(mom["violations"][0]) == 0
+    g = ctx.read(0)
+    ctx.close()
+    v1 = np.stack([g["vx"], g["vy"], g["vz"]]).astype(np.float64)
+    scale = np.abs(v0).sum()
+    assert np.abs(v1.sum(1) - v0.sum(1)).max() <= 3e-6 * scale
+    assert abs((v1 * v1).sum() - (v0 * v0).sum()) <= 3e-6 * (v0 * v0).sum()
+
+
+def test_level_majorant_rejected_with_reuse(trmc):
+    T = trmc
+    inst, v = case(T, 500, 0.05, T.ADAPTIVE_REUSE, 2, 40, T.FP64, T.MAJORANT_LEVEL)
+    with pytest.raises(T.TrmcError):
+        T.Context([inst], [T.device_particles(*v, precision=T.FP64)])

@@ -156,3 +156,42 @@ def test_decision_zero_stress_accepts(orc):
                         delta1=1e-9, delta2=2e-9, weight=1.0 / n)
     rec = inst.run(1)[0]
     assert rec.attempts == 1 and rec.m_state_after == 4
+
+
+def test_no_recompute_when_deeper_levels_stay_empty(orc):
+    """A recompute at a greater depth cannot change the step when the split,
+    continued from the remainder, puts no particle in any level up to m_cap:
+    the deeper trees are those of depth m.  Then the step is accepted at once
+    and keeps its depth, with the velocities a run at m_cap would give."""
+    n = 2000
+    vx, vy, vz = drifting_bimaxwellian(n, seed=26, stream=0)
+    # eps -> 0: q = 0, every level empty, everything thermalized; E1 = |T - S|/S > delta2
+    for m_init in (1, 2, 5):
+        inst = orc.Instance(vx, vy, vz, eps=1e-7, dt=0.05, trunc=orc.ADAPTIVE, m_init=m_init, m_cap=64,
+                            weight=1.0 / n)
+        rec = inst.run(1)[0]
+        assert rec.E1 > 0.1 and (rec.attempts, rec.m_used, rec.m_state_after) == (1, m_init, m_init)
+        deep = orc.Instance(vx, vy, vz, eps=1e-7, dt=0.05, trunc=orc.FIXED, m_init=64, m_cap=64, weight=1.0 / n)
+        deep.run(1)
+        assert np.array_equal(inst.vx, deep.vx) and np.array_equal(inst.vz, deep.vz)
+
+
+def test_recompute_only_when_a_deeper_level_fills(orc):
+    """Small q rem: whether the step is recomputed depends on the keyed draws of
+    the deeper levels alone.  Either it is accepted at once and equals the run
+    at m_cap bitwise (the deeper levels stayed empty), or it is recomputed."""
+    n = 3000
+    seen = {True: 0, False: 0}
+    for s in range(30):
+        vx, vy, vz = drifting_bimaxwellian(n, seed=27, stream=s)
+        # tau close to 1 with depth 4 of 8: a remainder of about q^... particles
+        kw = dict(eps=1.0, dt=9.0, alpha=0.0, uid=s, weight=1.0 / n, m_cap=8)
+        a = orc.Instance(vx, vy, vz, trunc=orc.ADAPTIVE, m_init=4, delta1=1e-12, delta2=2e-12, **kw)
+        rec = a.run(1)[0]
+        if rec.attempts == 1:
+            assert rec.m_state_after == 4
+            b = orc.Instance(vx, vy, vz, trunc=orc.FIXED, m_init=8, **kw)
+            b.run(1)
+            assert np.array_equal(a.vx, b.vx) and np.array_equal(a.vy, b.vy)
+        seen[rec.attempts == 1] += 1
+    assert seen[True] >= 3 and seen[False] >= 3
