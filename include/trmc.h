@@ -260,6 +260,26 @@ int trmc_fuse_steps(trmc_ctx* ctx, int on);
  * depend on it (every draw is keyed by its cell, not by its position). */
 int trmc_order_by_cost(trmc_ctx* ctx, int on);
 
+/* Allocation-free stepping, for callers that cannot allocate (code under stream
+ * capture, allocation-free serving loops): n_steps collision steps of ONE
+ * space-homogeneous instance, in place on the caller's device arrays b->vx,
+ * b->vy, b->vz (b->x unused), enqueued on hip_stream with no host wait, the
+ * same as trmc_init + trmc_step(n_steps) on a context holding only this
+ * instance (same kernels and kernel path: one wave below 1024 particles when
+ * m_cap <= 256, one workgroup otherwise), starting from m_init (adaptive
+ * depth) and step0.  Every working buffer (instance record, cell tables,
+ * per-cell scratch) lives in a static device array of 64 MiB per device, held
+ * until the process ends; no device or pinned memory is allocated.  Calls on
+ * one device share that array: calls that overlap on a device (other streams or
+ * host threads) race; a call reads nothing that an earlier call left there.
+ * No counters or moments are kept: use a context for those.
+ * Errors: TRMC_EINVAL for a bad descriptor or buffers, a slab, per-cell eps,
+ * saved depths, tree-shape truncation or TRMC_ADAPTIVE_REUSE; TRMC_ENOMEM when
+ * the instance's working memory exceeds the static array (about 300,000 FP32
+ * or 170,000 FP64 particles); TRMC_EIO for a HIP error.  A cell whose trees
+ * exceed its scratch is left unchanged, as in trmc_step. */
+int trmc_step_static(const trmc_desc* desc, const trmc_particles* b, uint32_t n_steps, void* hip_stream);
+
 /* Wait for the stream and report any asynchronous error. */
 int trmc_sync(trmc_ctx* ctx);
 

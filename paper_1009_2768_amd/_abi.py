@@ -20,7 +20,7 @@ EXPORTS = [
     "trmc_abi_version", "trmc_strerror", "trmc_workspace_size", "trmc_ctx_workspace_size", "trmc_init",
     "trmc_step", "trmc_moments", "trmc_state", "trmc_read", "trmc_admit", "trmc_retire", "trmc_sync",
     "trmc_destroy", "trmc_set_schedule", "trmc_get_schedule", "trmc_use_graph", "trmc_count",
-    "trmc_fuse_steps", "trmc_moments_async", "trmc_order_by_cost",
+    "trmc_fuse_steps", "trmc_moments_async", "trmc_order_by_cost", "trmc_step_static",
 ]
 
 SCHED_BUCKETS = 32
@@ -123,6 +123,8 @@ def load():
     L.trmc_fuse_steps.restype = i
     L.trmc_order_by_cost.argtypes = [vp, i]
     L.trmc_order_by_cost.restype = i
+    L.trmc_step_static.argtypes = [P(Desc), P(Particles), u32, vp]
+    L.trmc_step_static.restype = i
     L.trmc_moments_async.argtypes = [vp, u32, vp, u32]
     L.trmc_moments_async.restype = i
     L.trmc_count.argtypes = [vp, u32, P(ctypes.c_uint64)]

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrmc.so")
-SOURCES = ["runtime.hip", "k_collide.hip", "k_tiled.hip", "k_slab.hip"]
+SOURCES = ["runtime.hip", "k_collide.hip", "k_tiled.hip", "k_slab.hip", "noalloc.hip"]
 HEADERS = ["trmc_internal.h", "trmc_device.h", "collide_core.h"]
 
 FLAGS = [
