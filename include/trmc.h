@@ -10,7 +10,7 @@
  *
  * Conventions shared by every entry point
  *   - Return value: 0 on success, a negative errno-style code otherwise
- *     (TRMC_EINVAL, TRMC_ENOMEM, TRMC_ENOSPC, TRMC_EIO, TRMC_EOVERFLOW);
+ *     (TRMC_EINVAL, TRMC_ENOMEM, TRMC_ENOSPC, TRMC_EIO, TRMC_EOVERFLOW, TRMC_EBUSY);
  *     trmc_strerror() gives the text.  No exception crosses the ABI.
  *   - Arguments are validated before anything is enqueued; a failing call leaves
  *     the context unchanged.  Errors of asynchronous GPU work surface at the next
@@ -22,9 +22,15 @@
  *     (grown on demand, freed by trmc_destroy).
  *   - Work is enqueued on the HIP stream given at creation; calls on one context
  *     must come from one host thread at a time.
- *   - Results depend only on (descriptor, initial particles, number of steps):
- *     not on the slot an instance occupies, on the other instances in the batch,
- *     or on launch shapes.
+ *   - Results depend only on (descriptor, initial particles, number of steps)
+ *     and, in their last bits, on each cell's kernel path: not on the slot an
+ *     instance occupies, on the other instances in the batch, on the launch
+ *     order, on graph replay or on fused steps.  The kernel path of a cell (one
+ *     workgroup, one wave or the tile pipeline; trmc_set_schedule) fixes the
+ *     order of its FP64 cell sums, so two paths agree to rounding (FP64: within
+ *     1e-12 of the thermal speed), and an integer decision taken from such a sum
+ *     (the adaptive indicator at a threshold, the majorant's 20-bit grid) can in
+ *     rare cases differ; a fixed schedule table gives the same bits every run.
  */
 #ifndef TRMC_H
 #define TRMC_H
@@ -43,6 +49,7 @@ extern "C" {
 #define TRMC_ENOSPC (-28)
 #define TRMC_EIO (-5)
 #define TRMC_EOVERFLOW (-75)
+#define TRMC_EBUSY (-16)
 
 /* geometry */
 #define TRMC_HOMOG 1  /* one space-homogeneous cell (eq. HOM-r), no transport */
@@ -210,7 +217,9 @@ int trmc_count(trmc_ctx* ctx, uint32_t slot, uint64_t* n_live);
 
 /* Serving: add one instance while others run.  workspace: its own caller-owned
  * device memory of trmc_workspace_size(desc, 1) bytes.  On success *slot receives
- * the slot number.  TRMC_ENOSPC when the slot table or the cell capacity is full. */
+ * the slot number.  TRMC_ENOSPC when the slot table or the cell capacity is full;
+ * TRMC_EBUSY when the instance's device memory (workspace plus particle arrays)
+ * would take the active instances past the budget of trmc_set_budget. */
 int trmc_admit(trmc_ctx* ctx, const trmc_desc* desc, const trmc_particles* buf, void* workspace,
                size_t workspace_bytes, uint32_t* slot);
 
@@ -250,6 +259,14 @@ int trmc_use_graph(trmc_ctx* ctx, int on);
  * of a call when it can (see trmc_step); on == 0: one step after another, each
  * its own launches (or graph replay).  Results do not depend on it. */
 int trmc_fuse_steps(trmc_ctx* ctx, int on);
+
+/* Admission budget for serving: the device memory (workspace plus particle
+ * arrays, as trmc_workspace_size and the descriptor give it) that the active
+ * instances of the context may occupy together; 0 (the default) for none.
+ * trmc_admit fails with TRMC_EBUSY beyond it; trmc_retire gives an instance's
+ * memory back at once (the caller keeps its buffers alive until the stream has
+ * passed the instance's last step).  Lowering it retires nothing. */
+int trmc_set_budget(trmc_ctx* ctx, uint64_t bytes);
 
 /* Launch order (a scheduling choice, not a passage of the paper).  on != 0 (the
  * default): before each launch of the whole-cell kernels a device kernel sorts

@@ -240,6 +240,11 @@ class Context:
         self._admitted[slot.value] = (inst, particles, buf)
         return slot.value
 
+    def set_budget(self, nbytes: int):
+        """Device memory (workspaces and particle arrays) the active instances may
+        occupy; admit() raises TrmcError with code EBUSY beyond it (0: no budget)."""
+        check(self._lib.trmc_set_budget(self._ctx, int(nbytes)), "trmc_set_budget")
+
     def retire(self, slot: int):
         check(self._lib.trmc_retire(self._ctx, slot), "trmc_retire")
         self._admitted.pop(slot, None)

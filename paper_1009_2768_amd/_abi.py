@@ -13,7 +13,7 @@ WB_OFF, WB_MIN, WB_MEAN = 0, 1, 2
 BC_SPECULAR, BC_INFLOW = 0, 1
 MAJORANT_STEP, MAJORANT_LEVEL = 0, 1
 
-EINVAL, ENOMEM, ENOSPC, EIO, EOVERFLOW = -22, -12, -28, -5, -75
+EINVAL, ENOMEM, ENOSPC, EIO, EOVERFLOW, EBUSY = -22, -12, -28, -5, -75, -16
 CELL_OVERFLOW = 1
 
 EXPORTS = [
@@ -21,6 +21,7 @@ EXPORTS = [
     "trmc_step", "trmc_moments", "trmc_state", "trmc_read", "trmc_admit", "trmc_retire", "trmc_sync",
     "trmc_destroy", "trmc_set_schedule", "trmc_get_schedule", "trmc_use_graph", "trmc_count",
     "trmc_fuse_steps", "trmc_moments_async", "trmc_order_by_cost", "trmc_step_static",
+    "trmc_set_budget",
 ]
 
 SCHED_BUCKETS = 32
@@ -125,6 +126,8 @@ def load():
     L.trmc_order_by_cost.restype = i
     L.trmc_step_static.argtypes = [P(Desc), P(Particles), u32, vp]
     L.trmc_step_static.restype = i
+    L.trmc_set_budget.argtypes = [vp, ctypes.c_uint64]
+    L.trmc_set_budget.restype = i
     L.trmc_moments_async.argtypes = [vp, u32, vp, u32]
     L.trmc_moments_async.restype = i
     L.trmc_count.argtypes = [vp, u32, P(ctypes.c_uint64)]

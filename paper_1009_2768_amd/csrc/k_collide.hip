@@ -130,8 +130,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         const uint32_t pbits = perm_bits(n);
         const double c0 = (double)vx[0];  // shift for the one-pass P_xx
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        // loads of the next batch are issued before the current batch's role
-        // permutation is computed, so memory and ALU work overlap
+        // loads of the next batch are issued before the current batch is summed
         T ax[kUnroll], ay[kUnroll], az[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -161,7 +160,6 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                     s[1] += (double)ay[u];
                     s[2] += (double)az[u];
                     s[3] += dx * dx;
-                    M.role[i] = perm_inverse(i, n, pbits, pk);
                 }
             }
 #pragma unroll
@@ -170,6 +168,15 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                 ay[u] = by[u];
                 az[u] = bz[u];
             }
+        }
+        {
+            // roles: each wave takes a contiguous share of the slots, its lanes
+            // refilled as their cycle walks end (the walks vary in length)
+            constexpr uint32_t NW = G / 64;
+            const uint32_t w = tid >> 6;
+            const uint32_t share = (n + NW - 1u) / NW;
+            const uint32_t r0 = w * share, r1 = r0 + share < n ? r0 + share : n;
+            if (r0 < r1) roles_by_wave(M.role, r0, r1, n, pbits, pk);
         }
         gsum<G, 4>(s, gl.red);
         const double inv = 1.0 / (double)n;

@@ -161,7 +161,15 @@ struct Slot {
     InstDev host{};
     Layout lay{};
     uint64_t steps = 0;  // steps enqueued since admission
+    uint64_t bytes = 0;  // device memory of the instance: its workspace and particle arrays
 };
+
+// Device memory an instance occupies: its workspace and its particle arrays.
+uint64_t instance_bytes(const trmc_desc& d, const Layout& L)
+{
+    const uint64_t sz = d.precision == TRMC_FP64 ? 8 : 4;
+    return (uint64_t)L.total + sz * d.n_particles * (d.geometry == TRMC_SLAB1D ? 4u : 3u);
+}
 
 }  // namespace
 
@@ -190,6 +198,9 @@ struct trmc_ctx {
     InstDev** inst_ptrs = nullptr;
     uint32_t n_active = 0;
     uint32_t cells_used = 0;
+    // admission budget of device memory (trmc_set_budget; 0: none) and the
+    // memory of the active instances
+    uint64_t budget = 0, used = 0;
     std::vector<Slot> slots;
     int sticky = 0;
     uint32_t sched[TRMC_SCHED_BUCKETS] = {};  // TRMC_PATH_* per bucket of cell size
@@ -407,6 +418,8 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
     if (bytes < L.total) return TRMC_ENOMEM;
     const uint32_t nc = d->geometry == TRMC_SLAB1D ? d->n_cells : 1u;
     if (c->cells_used + nc > c->max_cells) return TRMC_ENOSPC;
+    const uint64_t need = instance_bytes(*d, L);
+    if (c->budget && c->used + need > c->budget) return TRMC_EBUSY;
     uint32_t slot = UINT32_MAX;
     for (uint32_t i = 0; i < c->slots.size(); ++i)
         if (!c->slots[i].active) { slot = i; break; }
@@ -504,11 +517,14 @@ int admit_one(trmc_ctx* c, const trmc_desc* d, const trmc_particles* b, unsigned
         return TRMC_EIO;
     }
     s.active = true;
+    s.bytes = need;
     c->cells_used += nc;
+    c->used += need;
     rc = rebuild ? rebuild_tables(c) : 0;
     if (rc) {
         s.active = false;
         c->cells_used -= nc;
+        c->used -= need;
         return rc;
     }
     *slot_out = slot;
@@ -609,6 +625,7 @@ const char* trmc_strerror(int status)
     case TRMC_ENOSPC: return "no free instance slot or cell capacity";
     case TRMC_EIO: return "HIP runtime error";
     case TRMC_EOVERFLOW: return "a cell's collision trees exceeded the scratch capacity (cell left unchanged)";
+    case TRMC_EBUSY: return "admission would exceed the context's device-memory budget";
     default: return "unknown status";
     }
 }
@@ -722,6 +739,7 @@ int trmc_retire(trmc_ctx* c, uint32_t slot)
     Slot& s = c->slots[slot];
     s.active = false;
     c->cells_used -= s.host.n_cells;
+    c->used -= s.bytes;
     c->tables_dirty = true;  // no step is enqueued for it from now on
     return 0;
 }
@@ -887,6 +905,13 @@ int trmc_fuse_steps(trmc_ctx* c, int on)
     if (!c) return TRMC_EINVAL;
     if (c->sticky) return c->sticky;
     c->fuse = on != 0;
+    return 0;
+}
+
+int trmc_set_budget(trmc_ctx* c, uint64_t bytes)
+{
+    if (!c) return TRMC_EINVAL;
+    c->budget = bytes;
     return 0;
 }
 

@@ -56,8 +56,11 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo_a = 0xD2511F53u * c0, hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2, hi_b = __umulhi(0xCD9E8D57u, c2);
+        // one 32x32->64 product each (v_mad_u64_u32) instead of separate low and
+        // high halves (v_mul_lo_u32 + v_mul_hi_u32): half the multiplies
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0, pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo_a = (uint32_t)pa, hi_a = (uint32_t)(pa >> 32);
+        const uint32_t lo_b = (uint32_t)pb, hi_b = (uint32_t)(pb >> 32);
         const uint32_t n0 = hi_b ^ c1 ^ k0;
         const uint32_t n2 = hi_a ^ c3 ^ k1;
         c0 = n0;
@@ -200,6 +203,36 @@ __device__ __forceinline__ uint32_t perm_inverse(uint32_t s, uint32_t n, uint32_
     uint32_t y = feistel_dec(s, b, k);
     while (y >= n) y = feistel_dec(y, b, k);
     return y;
+}
+
+// Role index of every slot in [r0, r1) of a cell, written to role[], by one
+// wave whose lanes take the next slot as soon as their cycle walk ends: a wave
+// evaluates about (sum of the walks) / 64 rounds of the network instead of the
+// longest walk of its 64 slots per batch of 64.
+__device__ __forceinline__ void roles_by_wave(__attribute__((address_space(1))) uint32_t* role, uint32_t r0,
+                                              uint32_t r1, uint32_t n, uint32_t b, uint4 k)
+{
+    const uint32_t lane = __lane_id();
+    uint32_t cur = 0xFFFFFFFFu, val = 0, base = r0;
+    for (;;) {
+        // lanes without a slot take the next ones in order
+        const bool need = cur == 0xFFFFFFFFu;
+        const unsigned long long m = __ballot(need);
+        const uint32_t cand = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        base += (uint32_t)__popcll(m);
+        if (need && cand < r1) {
+            cur = cand;
+            val = cand;
+        }
+        if (__ballot(cur != 0xFFFFFFFFu) == 0ull) break;
+        if (cur != 0xFFFFFFFFu) {
+            val = feistel_dec(val, b, k);
+            if (val < n) {
+                role[cur] = val;
+                cur = 0xFFFFFFFFu;
+            }
+        }
+    }
 }
 
 // The rounds in forward order: perm_forward(i) is the slot of role index i

@@ -33,8 +33,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _abi
-from . import (ADAPTIVE, FP32_MIXED, FP64, HOMOG, SLAB1D, Context, Instance, check, moments_record_bytes,
-               unpack_moments)
+from . import (ADAPTIVE, FP32_MIXED, FP64, HOMOG, SLAB1D, Context, Instance, TrmcError, check,
+               moments_record_bytes, unpack_moments)
 
 
 def instance_of(req, precision=FP32_MIXED, m_cap=64) -> Instance:
@@ -135,8 +135,15 @@ class Server:
                 and self.cells + cells <= self.max_cells)
 
     def admit(self, req, inst, nbytes, now):
+        """Admit a request (its memory was checked by fits()); None when the
+        library's own budget check (trmc_admit, active instances only) refuses it."""
         parts = self.initial(req, dtype=self.dtype)
-        slot = self.ctx.admit(inst, parts)
+        try:
+            slot = self.ctx.admit(inst, parts)
+        except TrmcError as e:
+            if e.code == _abi.EBUSY:
+                return None
+            raise
         self.active[slot] = [req, int(req["steps"]), nbytes, now, parts, self.ticks]
         self.used += nbytes
         self.cells += int(req["n_cells"]) if req["slab"] else 1
@@ -202,6 +209,7 @@ class Server:
         at most that many ticks later).  Returns the list of Done records in
         completion order."""
         import torch
+        self.ctx.set_budget(self.budget)  # the library refuses admissions beyond it too (TRMC_EBUSY)
         ticks_ev = []  # (start, end) events of every tick on the context's stream
         pending = deque(sorted(requests, key=lambda r: r["arrival"]))
         waiting = deque()
@@ -221,11 +229,11 @@ class Server:
                 if head is None:
                     head = self.cost(waiting[0])
                 inst, nbytes = head
-                if not self.fits(waiting[0], nbytes):
+                if not self.fits(waiting[0], nbytes) or self.admit(waiting[0], inst, nbytes, now) is None:
                     if not self.active and not self.draining:
                         raise RuntimeError(f"request {waiting[0]['rid']} does not fit in an empty server")
                     break
-                self.admit(waiting.popleft(), inst, nbytes, now)
+                waiting.popleft()
                 head = None
             if not self.active:
                 if self.draining:

@@ -139,3 +139,35 @@ def test_request_larger_than_budget_is_rejected(T):
     with pytest.raises(RuntimeError):
         srv.run(reqs, realtime=False)
     srv.close()
+
+
+def test_admission_budget_behind_the_abi(T):
+    """trmc_set_budget / TRMC_EBUSY: admissions beyond the device-memory budget of
+    the active instances fail and change nothing; a retirement makes room."""
+    from paper_1009_2768_amd import _abi
+    from paper_1009_2768_amd.serve import Server, instance_of
+    reqs = W.serving_requests(rate=100.0, duration=0.2, seed=6, n_min=2000, n_max=3000, steps_min=2,
+                              steps_max=3, slab_fraction=0.0)
+    assert len(reqs) >= 4
+    srv = Server(hbm_budget=1 << 40, precision=T.FP32_MIXED, max_instances=8, max_cells=64)
+    cost = [srv.cost(r)[1] for r in reqs[:4]]
+    ctx = srv.ctx
+    ctx.set_budget(cost[0] + cost[1])
+    s0 = ctx.admit(instance_of(reqs[0]), W.serving_initial(reqs[0]))
+    s1 = ctx.admit(instance_of(reqs[1]), W.serving_initial(reqs[1]))
+    with pytest.raises(T.TrmcError) as e:
+        ctx.admit(instance_of(reqs[2]), W.serving_initial(reqs[2]))
+    assert e.value.code == _abi.EBUSY
+    ctx.step(1)
+    ctx.sync()
+    ctx.retire(s0)
+    if cost[2] <= cost[0]:
+        s2 = ctx.admit(instance_of(reqs[2]), W.serving_initial(reqs[2]))
+        ctx.step(1)
+        ctx.sync()
+        assert s2 != s1
+    ctx.set_budget(0)  # no budget: anything that fits the slot table is admitted
+    ctx.admit(instance_of(reqs[3]), W.serving_initial(reqs[3]))
+    ctx.step(1)
+    ctx.sync()
+    srv.close()
