@@ -9,8 +9,9 @@ metric is particle-steps per second over the timed steps (state resident in HBM)
 
 The headline (value, roofline) is measured first.  Then, by default, the legs
 cpu (the oracle on host threads), batching (batched against one instance at a
-time) and serving (a Poisson request stream, and the same requests all queued
-at once); --legs adds fusion, reuse, shock, tubes and wb.  A watchdog prints the
+time), serving (a Poisson request stream, and the same requests all queued at
+once) and precision (FP32 against FP64 per cell moment on the 10^7-particle
+transition tube over 500 steps); --legs adds fusion, reuse, shock, tubes and wb.  A watchdog prints the
 line after --budget seconds with the legs not reached listed as skipped.
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
@@ -492,7 +493,68 @@ def serving(T, args):
     return out
 
 
-LEGS_DEFAULT = ("cpu", "batching", "serving")
+def precision_c4(T, seed, steps=500, every=10, average_from=250):
+    """FP32-mixed against FP64 on the transition-regime tube (10^4 cells, 1778 / 222
+    particles per cell, about 10^7 particles, eps(x) log-linear from 1e-4 to 1,
+    hard spheres, adaptive depth, dt = CFL 0.5), 500 steps from the same initial
+    particles.  FP64 stands for the oracle, which it matches to 1e-12 at this size
+    (one step, tests).  The two precisions draw the same keyed random numbers but
+    their trajectories part within a few steps (a rounding moves an integer
+    decision), so the per-cell differences are compared with two FP64 runs of
+    different seeds (the noise floor).  Per cell moment (density, u_x over the
+    thermal speed, T, P_xx): median / 99th percentile / largest relative
+    difference, at the last step and averaged over the steps from average_from on."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    nc = 10000
+    x, vx, vy, vz, w = W.sod(nc, 1778, 222, seed=seed)
+    e = W.transition_eps(nc)
+
+    def run(precision, sd):
+        inst = T.Instance(n_particles=len(x), geometry=T.SLAB1D, n_cells=nc, dt=W.sod_dt(1.0, nc), eps=1.0,
+                          eps_cells=e, alpha=1.0, trunc=T.ADAPTIVE, m_init=2, m_cap=64, particle_weight=w,
+                          uid=9000, seed=sd, precision=precision)
+        ctx = T.Context([inst], [T.device_particles(vx, vy, vz, x, precision)])
+        ctx.use_graph(True)
+        acc, k = None, 0
+        t0 = time.perf_counter()
+        for s in range(steps // every):
+            ctx.step(every)
+            if (s + 1) * every > average_from:
+                m = ctx.moments(0)
+                cur = np.stack([m["rho"], m["ux"] / np.sqrt(np.maximum(m["T"], 1e-300)), m["T"], m["Pxx"]])
+                acc = cur if acc is None else acc + cur
+                k += 1
+        ctx.sync()
+        wall = time.perf_counter() - t0
+        ctx.close()
+        torch.cuda.empty_cache()
+        return cur, acc / k, wall
+
+    f32, f32avg, w32 = run(T.FP32_MIXED, seed)
+    f64, f64avg, w64 = run(T.FP64, seed)
+    g64, g64avg, _ = run(T.FP64, seed + 1)
+    names = ["rho", "ux_over_thermal_speed", "T", "Pxx"]
+
+    def stats(a, b):
+        out = {}
+        for j, nm in enumerate(names):
+            d = np.abs(a[j] - b[j]) / (1.0 if j == 1 else np.abs(b[j]))
+            out[nm] = {"median": float(np.median(d)), "p99": float(np.quantile(d, 0.99)), "max": float(d.max())}
+        return out
+
+    return {"workload": f"transition-regime tube, {nc} cells, {len(x)} particles, eps(x) 1e-4..1, hard spheres, "
+                        f"adaptive depth, {steps} steps",
+            "fp32_vs_fp64_last_step": stats(f32, f64), "fp64_vs_fp64_other_seed_last_step": stats(g64, f64),
+            "fp32_vs_fp64_time_averaged": stats(f32avg, f64avg),
+            "fp64_vs_fp64_other_seed_time_averaged": stats(g64avg, f64avg),
+            "averaged_over": f"every {every}th step from step {average_from + every} to {steps}",
+            "fp32_s": w32, "fp64_s": w64}
+
+
+LEGS_DEFAULT = ("cpu", "batching", "serving", "precision")
 LEGS_ALL = LEGS_DEFAULT + ("fusion", "reuse", "shock", "tubes", "wb")
 
 
@@ -679,6 +741,9 @@ def main():
         elif leg == "serving":
             res = serving(T, args)
             out.d["serving"] = res
+        elif leg == "precision":
+            res = precision_c4(T, args.seed)
+            out.d["precision_transition_tube"] = res
         elif leg == "fusion":
             if not fuse:
                 res = {"skipped": "steps are not fused on this schedule"}
