@@ -377,6 +377,36 @@ __device__ __forceinline__ double majorant_of(double alpha, double d2)
     return grid_up20(alpha == 1.0 ? two_dv : pow(two_dv, alpha));
 }
 
+// The VHS majorant without a pass over the velocities for their largest
+// distance to the mean, when a bracket settles it.  With d2c the largest squared
+// distance of the velocities to a point c and delta = |mean - c|, the largest
+// distance dv to the mean lies in [sqrt(d2c) - delta, sqrt(d2c) + delta]
+// (triangle inequality).  Both ends are widened by far more than the rounding
+// of either computation (and, for alpha < 1, of pow); if the widened ends give
+// the same majorant on the 20-bit grid, majorant_of is monotone in between, so
+// that is also the majorant of the exact largest distance.  Returns a d2 whose
+// majorant_of is that value (the upper end), or -1 when the bracket does not
+// settle it (the caller makes the exact pass).  0 < alpha <= 1.
+__device__ __forceinline__ double majorant_bracket(double alpha, double d2c, double delta)
+{
+#pragma clang fp contract(off)
+    if (!(d2c >= 0.0 && d2c <= 1e300 && delta >= 0.0 && delta <= 1e300)) return -1.0;
+    const double r = sqrt(d2c);
+    const double lo_r = r * (1.0 - 1e-12) - delta * (1.0 + 1e-12);
+    if (!(lo_r > 0.0)) return -1.0;
+    const double hi_r = r * (1.0 + 1e-12) + delta * (1.0 + 1e-12);
+    const double lo = lo_r * lo_r * (1.0 - 1e-12), hi = hi_r * hi_r * (1.0 + 1e-12);
+    double glo, ghi;
+    if (alpha == 1.0) {
+        glo = grid_up20(2.0 * sqrt(lo));
+        ghi = grid_up20(2.0 * sqrt(hi));
+    } else {
+        glo = grid_up20(pow(2.0 * sqrt(lo), alpha) * (1.0 - 1e-14));
+        ghi = grid_up20(pow(2.0 * sqrt(hi), alpha) * (1.0 + 1e-14));
+    }
+    return glo == ghi ? hi : -1.0;
+}
+
 // Majorant, relaxation parameter and depth of the step from the cell's moments
 // (thread 0 of the group): g = (2 dv)^alpha on the 20-bit grid, mu = rho g,
 // q = exp(-mu dt / eps) (Sec. 3.2, Sec. 4.2); m from the truncation mode.
@@ -1055,6 +1085,9 @@ __device__ __forceinline__ void write_stats(CellStats* st, uint32_t n, const Cel
     s.q = sh.q;
     s.g = sh.g_last;
     s.E1 = sh.E1;
+    s.mean[0] = sh.mean[0];
+    s.mean[1] = sh.mean[1];
+    s.mean[2] = sh.mean[2];
     *st = s;
 }
 

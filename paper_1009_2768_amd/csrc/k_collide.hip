@@ -73,6 +73,10 @@ __device__ unsigned long long g_span[16384][2];
 #ifndef TRMC_WRITE_UNROLL
 #define TRMC_WRITE_UNROLL 4
 #endif
+#ifndef TRMC_MAJ_BRACKET
+#define TRMC_MAJ_BRACKET 1
+#endif
+constexpr bool kMajBracket = TRMC_MAJ_BRACKET != 0;  // the majorant bracket of workgroup cells
 constexpr int kUnroll = TRMC_SLOT_UNROLL;  // slots per thread per batch in the moment and normal passes
 
 // One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
@@ -130,6 +134,18 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         const uint32_t pbits = perm_bits(n);
         const double c0 = (double)vx[0];  // shift for the one-pass P_xx
         double s[4] = {0.0, 0.0, 0.0, 0.0};
+        // VHS cells of a workgroup: the largest distance to the previous step's
+        // mean (this group's last step of the cell, else the cell's record from
+        // the last launch) brackets the majorant; the exact pass below runs only
+        // when the bracket does not settle it.  Collisions conserve momentum, so
+        // the two means differ by rounding only.
+        const bool bk = kMajBracket && !DYN && G > 64 && uni((uint64_t)__double_as_longlong(I->alpha)) != 0ull;
+        double bc0 = 0.0, bc1 = 0.0, bc2 = 0.0, d2c = 0.0;
+        if (bk) {
+            bc0 = soff > 0 ? sh.mean[0] : st->mean[0];
+            bc1 = soff > 0 ? sh.mean[1] : st->mean[1];
+            bc2 = soff > 0 ? sh.mean[2] : st->mean[2];
+        }
         // loads of the next batch are issued before the current batch is summed
         T ax[kUnroll], ay[kUnroll], az[kUnroll];
 #pragma unroll
@@ -160,6 +176,11 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                     s[1] += (double)ay[u];
                     s[2] += (double)az[u];
                     s[3] += dx * dx;
+                    if (bk) {
+                        const double ex = (double)ax[u] - bc0, ey = (double)ay[u] - bc1, ez = (double)az[u] - bc2;
+                        const double e2 = ex * ex + ey * ey + ez * ez;
+                        d2c = e2 > d2c ? e2 : d2c;
+                    }
                 }
             }
 #pragma unroll
@@ -183,7 +204,13 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         const double dxm = s[0] * inv;
         const double mx = c0 + dxm, my = s[1] * inv, mz = s[2] * inv;
         double dmax = 0.0;
-        if (uni((uint64_t)__double_as_longlong(I->alpha)) != 0ull) {
+        if (bk) {
+            // every thread reduces the same values in the same order: a uniform verdict
+            const double d2 = gmax<G>(d2c, gl.red);
+            const double ex = mx - bc0, ey = my - bc1, ez = mz - bc2;
+            dmax = majorant_bracket(I->alpha, d2, sqrt(ex * ex + ey * ey + ez * ez));
+        }
+        if (uni((uint64_t)__double_as_longlong(I->alpha)) != 0ull && !(dmax >= 0.0 && bk)) {
             // two batches of loads in flight: the next batch is issued before
             // the current one is reduced
             double d2max = 0.0;

@@ -50,6 +50,7 @@ struct CellStats {
     uint32_t ticks;  // wall-clock duration of the cell's step (100 MHz counter): its cost in the launch order
     unsigned long long collisions, dummies, violations, work_collisions;
     double q, g, E1;
+    double mean[3];  // the step's pre-collision mean velocity (centre of the next step's majorant bracket)
 };
 
 // One instance, resident in its workspace.  Kernels read parameters from here;
