@@ -744,7 +744,9 @@ __device__ __forceinline__ uint32_t leaf_role(uint32_t r, uint32_t N0, uint32_t 
 // find their whole pool in rank order.  sums = {kept (vx-m)^2, thermalized
 // (vx-m)^2, thermalized v-m (3), thermalized |v-m|^2}.  Roles below kept_end
 // are unchanged, roles from leaf_end on are thermalized, the others are leaves.
-template <typename T, int NT>
+// ALL_TH: an attempt with no unchanged slots and no leaves (kept_end = leaf_end
+// = 0), whose roles are not read: every slot is thermalized.
+template <typename T, int NT, bool ALL_TH = false>
 __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, gptr<const T> vz,
                                             gptr<const uint32_t> role, gptr<Pack4<T>> leaf,
                                             uint32_t n, uint32_t N0, uint32_t s_begin, uint32_t s_end,
@@ -763,7 +765,7 @@ __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, 
         for (int u = 0; u < U; ++u) {
             const uint32_t i = s0 + u * NT;
             const bool ok = i < s_end;
-            ro[u] = ok ? role[i] : 0xFFFFFFFFu;
+            ro[u] = ok ? (ALL_TH ? leaf_end : role[i]) : 0xFFFFFFFFu;
             ax[u] = ok ? vx[i] : T(0);
             ay[u] = ok ? vy[i] : T(0);
             az[u] = ok ? vz[i] : T(0);

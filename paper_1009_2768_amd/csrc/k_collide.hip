@@ -77,6 +77,10 @@ __device__ unsigned long long g_span[16384][2];
 #define TRMC_MAJ_BRACKET 1
 #endif
 constexpr bool kMajBracket = TRMC_MAJ_BRACKET != 0;  // the majorant bracket of workgroup cells
+#ifndef TRMC_LAZY_ROLES
+#define TRMC_LAZY_ROLES 1
+#endif
+constexpr bool kLazyRoles = TRMC_LAZY_ROLES != 0;  // roles made after the split for cells predicted all-thermalized
 constexpr int kUnroll = TRMC_SLOT_UNROLL;  // slots per thread per batch in the moment and normal passes
 
 // One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
@@ -127,11 +131,33 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     M.init(I, off, cell, n);
     Levels L = levels_at(lds_levels + (size_t)grp * 5u * lv_stride, lv_stride);
 
+    // Roles: each wave takes a contiguous share of the slots, its lanes refilled
+    // as their cycle walks end (the walks vary in length).
+    auto make_roles = [&]() {
+        const uint4 pk = draw(key, 0, TAG_PERM, 0);
+        const uint32_t pbits = perm_bits(n);
+        constexpr uint32_t NW = G / 64;
+        const uint32_t w = tid >> 6;
+        const uint32_t share = (n + NW - 1u) / NW;
+        const uint32_t r0 = w * share, r1 = r0 + share < n ? r0 + share : n;
+        if (r0 < r1) roles_by_wave(M.role, r0, r1, n, pbits, pk);
+    };
+    // A cell whose previous step thermalized every particle (small eps) most
+    // likely does so again: its roles are not made up front.  An attempt that
+    // keeps or collides any particle makes them after its split; while none
+    // has, every slot is thermalized and the slot passes read no roles.  The
+    // sums are the same either way (same slots, same order).
+    bool roles_ready = true;
+    if constexpr (kLazyRoles && !WB && !REUSE) {
+        // the cell's record of its last step (this group's own previous step in a
+        // fused launch: ordered by the group barrier between the steps)
+        const bool all_th = st->n == n && st->N0 == 0u && st->n_th == n && st->status == 0u;
+        roles_ready = !uni((uint32_t)all_th);
+    }
+
     TRMC_PHASE_BEGIN();
     // ---- 1-2. moments, roles, parameters of the step ------------------------
     {
-        const uint4 pk = draw(key, 0, TAG_PERM, 0);
-        const uint32_t pbits = perm_bits(n);
         const double c0 = (double)vx[0];  // shift for the one-pass P_xx
         double s[4] = {0.0, 0.0, 0.0, 0.0};
         // VHS cells of a workgroup: the largest distance to the previous step's
@@ -190,15 +216,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                 az[u] = bz[u];
             }
         }
-        {
-            // roles: each wave takes a contiguous share of the slots, its lanes
-            // refilled as their cycle walks end (the walks vary in length)
-            constexpr uint32_t NW = G / 64;
-            const uint32_t w = tid >> 6;
-            const uint32_t share = (n + NW - 1u) / NW;
-            const uint32_t r0 = w * share, r1 = r0 + share < n ? r0 + share : n;
-            if (r0 < r1) roles_by_wave(M.role, r0, r1, n, pbits, pk);
-        }
+        if (roles_ready) make_roles();
         gsum<G, 4>(s, gl.red);
         const double inv = 1.0 / (double)n;
         const double dxm = s[0] * inv;
@@ -307,6 +325,11 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
 
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
         const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
+        if (!roles_ready && leaf_end != 0u) {
+            make_roles();
+            gsync<G>();  // roles visible to the gather
+            roles_ready = true;
+        }
         double sums[6] = {0, 0, 0, 0, 0, 0};
         const bool no_borrow = R0 <= P;
         if (pooled && no_borrow) {
@@ -321,9 +344,14 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
             }
             if (tid == 0) sums[0] = sh.kept0;
         } else {
-            const bool pool_all = attempt > 0 && no_borrow;
-            gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done, pool_all,
-                              mx, my, mz, tid, sums);
+            // (an attempt without roles keeps no pool: its slots' ranks are not known)
+            const bool pool_all = attempt > 0 && no_borrow && roles_ready;
+            if (roles_ready)
+                gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done,
+                                  pool_all, mx, my, mz, tid, sums);
+            else
+                gather_sets<T, G, true>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done,
+                                        pool_all, mx, my, mz, tid, sums);
             leaves_done = pool_all ? P : (R0 > leaves_done ? R0 : leaves_done);
             pooled = pool_all;
         }
@@ -463,7 +491,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t i = s0 + u * G;
-                ro[u] = i < n ? M.role[i] : 0u;
+                ro[u] = i < n ? (roles_ready ? M.role[i] : leaf_end) : 0u;
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -505,7 +533,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {
                 const uint32_t s = s0 + u * G;
-                ro[u] = s < n ? M.role[s] : 0u;
+                ro[u] = s < n ? (roles_ready ? M.role[s] : leaf_end) : 0u;
             }
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {

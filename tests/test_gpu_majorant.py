@@ -125,3 +125,43 @@ def test_level_majorant_rejected_with_reuse(trmc):
     inst, v = case(T, 500, 0.05, T.ADAPTIVE_REUSE, 2, 40, T.FP64, T.MAJORANT_LEVEL)
     with pytest.raises(T.TrmcError):
         T.Context([inst], [T.device_particles(*v, precision=T.FP64)])
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_step_majorant_every_step_single_and_fused_fp64(trmc, orc, alpha):
+    """The step's majorant (Sec. 4.2) of a workgroup cell, step by step: taken
+    from the bracket around the previous step's mean when it settles the grid
+    value, else from the exact pass; either way equal to the oracle's, in single
+    steps (the previous launch's record) and in fused steps (the group's last
+    step)."""
+    T = trmc
+    n, steps = 6000, 8
+    say("step majorant every step, group, alpha", alpha)
+    v = W.shell(n, seed=43, stream=7)
+    mk = lambda: T.Instance(n_particles=n, eps=0.1, alpha=alpha, trunc=T.FIXED, m_init=6, m_cap=64, uid=77, seed=3,
+                            dt=0.05, precision=T.FP64, particle_weight=1.0 / n)
+    o = orc.Instance(*v, eps=0.1, alpha=alpha, trunc=orc.FIXED, m_init=6, m_cap=64, uid=77, seed=3, dt=0.05,
+                     weight=1.0 / n)
+    ctx = T.Context([mk()], [T.device_particles(*v, precision=T.FP64)])
+    ctx.set_schedule([T.PATH_GROUP] * T.SCHED_BUCKETS)
+    for s in range(steps):
+        ctx.step(1)
+        o.run(1)
+        mom, r = ctx.moments(0), o.last[0]
+        assert float(mom["g"][0]) == r.g, (s, float(mom["g"][0]), r.g)
+        for gk, ok in (("collisions", "collisions"), ("dummies", "dummies"), ("violations", "violations")):
+            assert int(mom[gk][0]) == int(getattr(r, ok)), (s, gk)
+    single = ctx.read(0)
+    ctx.close()
+    ctx = T.Context([mk()], [T.device_particles(*v, precision=T.FP64)])
+    ctx.set_schedule([T.PATH_GROUP] * T.SCHED_BUCKETS)
+    ctx.step(steps)
+    fused, mom = ctx.read(0), ctx.moments(0)
+    ctx.close()
+    assert float(mom["g"][0]) == o.last[0].g
+    for c in ("vx", "vy", "vz"):
+        assert np.array_equal(fused[c], single[c]), c
+    ov = np.stack([o.vx, o.vy, o.vz], 1)
+    gv = np.stack([single["vx"], single["vy"], single["vz"]], 1)
+    err = float(np.abs(gv - ov).max() / math.sqrt(ov.var(0).sum() / 3.0))
+    assert err <= 1e-12, err

@@ -1,0 +1,77 @@
+"""GPU: cells whose previous step thermalized every particle make their role
+permutation (a6) only when an attempt keeps or collides a particle.  At an eps
+where the split (Alg. 4.2) leaves a cell sometimes wholly thermalized and
+sometimes not, every step's integers equal the FP64 oracle's, the velocities
+stay within 1e-12 of it, and fused steps equal single steps bitwise; on the
+workgroup and the wave path, with fixed and adaptive depth."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trmc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm GPU"
+    import paper_1009_2768_amd as T
+    T.load()
+    return T
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+# Maxwell molecules (g = 1, rho = 1): q = exp(-dt / eps) = 1 / (f n); f chosen so
+# that about half the steps (adaptive: with redos) thermalize the whole cell
+CASES = {"group": 2000, "wave": 300}
+FACTOR = {"fixed": 16.0, "adaptive": 100.0}
+
+
+@pytest.mark.parametrize("path", ["group", "wave"])
+@pytest.mark.parametrize("trunc", ["fixed", "adaptive"])
+def test_roles_when_needed_match_oracle(trmc, orc, path, trunc):
+    T = trmc
+    n, steps = CASES[path], 40
+    eps = 0.05 / math.log(FACTOR[trunc] * n)
+    say("roles when needed", path, trunc, "n", n, "eps", f"{eps:.4g}")
+    v = W.bkw(n, 0.6, 0, 321)
+    tr, otr = (T.FIXED, orc.FIXED) if trunc == "fixed" else (T.ADAPTIVE, orc.ADAPTIVE)
+    mk = lambda: T.Instance(n_particles=n, eps=eps, alpha=0.0, trunc=tr, m_init=2, m_cap=64, uid=5, seed=11,
+                            dt=0.05, precision=T.FP64, particle_weight=1.0 / n)
+    p = T.PATH_GROUP if path == "group" else T.PATH_WAVE
+    o = orc.Instance(*v, eps=eps, alpha=0.0, trunc=otr, m_init=2, m_cap=64, uid=5, seed=11, dt=0.05,
+                     weight=1.0 / n)
+    ctx = T.Context([mk()], [T.device_particles(*v, precision=T.FP64)])
+    ctx.set_schedule([p] * T.SCHED_BUCKETS)
+    whole = 0
+    for s in range(steps):
+        ctx.step(1)
+        o.run(1)
+        mom, r = ctx.moments(0), o.last[0]
+        for gk, ok in (("N0", "N0"), ("R0", "R0"), ("thermalized", "n_th"), ("collisions", "collisions"),
+                       ("dummies", "dummies"), ("attempts", "attempts"), ("m_used", "m_used")):
+            assert int(mom[gk][0]) == int(getattr(r, ok)), (s, gk, int(mom[gk][0]), int(getattr(r, ok)))
+        whole += int(r.n_th) == n
+    single = ctx.read(0)
+    ctx.close()
+    say(f"{whole} of {steps} steps thermalized the whole cell")
+    assert 5 <= whole <= steps - 5, whole  # both kinds of step, and the changes between them
+    ov = np.stack([o.vx, o.vy, o.vz], 1)
+    gv = np.stack([single["vx"], single["vy"], single["vz"]], 1)
+    err = float(np.abs(gv - ov).max() / math.sqrt(ov.var(0).sum() / 3.0))
+    assert err <= 1e-12, err
+    ctx = T.Context([mk()], [T.device_particles(*v, precision=T.FP64)])
+    ctx.set_schedule([p] * T.SCHED_BUCKETS)
+    ctx.step(steps)
+    fused = ctx.read(0)
+    ctx.close()
+    for c in ("vx", "vy", "vz"):
+        assert np.array_equal(fused[c], single[c]), c
