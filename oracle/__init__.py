@@ -65,6 +65,36 @@ class CellRecord(ctypes.Structure):
     ]
 
 
+class AttemptRecord(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint32), ("N0", ctypes.c_uint32), ("m", ctypes.c_uint32), ("me", ctypes.c_uint32),
+        ("mprev", ctypes.c_uint32), ("folds", ctypes.c_uint32),
+        ("R0prev", ctypes.c_uint64), ("R0", ctypes.c_uint64), ("ncoll", ctypes.c_uint64),
+        ("sum_R", ctypes.c_uint64), ("max_C", ctypes.c_uint64), ("coff_max", ctypes.c_uint64),
+        ("borrowed", ctypes.c_uint64), ("n_th", ctypes.c_uint64),
+    ]
+
+
+class AttemptLog:
+    """Integer outline of every attempt of the cell steps run on this thread
+    inside the with-block (see orc_attempt): a list of dicts in .records."""
+
+    def __init__(self, cap=1 << 16):
+        self.buf = (AttemptRecord * cap)()
+        self.cap = cap
+        self.records = []
+
+    def __enter__(self):
+        lib().orc_attempt_log(self.buf, self.cap)
+        return self
+
+    def __exit__(self, *exc):
+        k = lib().orc_attempt_log(None, 0)
+        names = [f for f, _ in AttemptRecord._fields_]
+        self.records = [{f: int(getattr(self.buf[i], f)) for f in names} for i in range(min(k, self.cap))]
+        return False
+
+
 _lib = None
 
 
@@ -104,6 +134,8 @@ def lib():
         L.orc_tree.restype = ctypes.c_int64
         L.orc_wb_len.argtypes = [dbl, dbl, u32]
         L.orc_wb_len.restype = dbl
+        L.orc_attempt_log.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        L.orc_attempt_log.restype = ctypes.c_uint64
         _lib = L
     return _lib
 

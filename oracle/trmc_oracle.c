@@ -456,6 +456,18 @@ static void tree_lengths(const tree_t* t, uint32_t kind, double** lens, double* 
     }
 }
 
+static __thread orc_attempt* g_alog;
+static __thread uint64_t g_alog_cap, g_alog_n;
+
+uint64_t orc_attempt_log(orc_attempt* buf, uint64_t cap)
+{
+    const uint64_t n = g_alog_n;
+    g_alog = buf;
+    g_alog_cap = buf ? cap : 0;
+    g_alog_n = 0;
+    return n;
+}
+
 static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_state, orc_cell_record* rec)
 {
     memset(rec, 0, sizeof *rec);
@@ -575,6 +587,29 @@ static void cell_step(const cell_params* cp, uint32_t n, vec3* v, uint32_t* m_st
         ro.borrowed = ro.R0 > ro.P ? ro.R0 - ro.P : 0;
         ro.n_th = ro.R0 < ro.P ? ro.P - ro.R0 : 0;
         memcpy(ro.pk, pk, sizeof pk);
+        if (g_alog && g_alog_n < g_alog_cap) {
+            orc_attempt* a = &g_alog[g_alog_n++];
+            a->n = n;
+            a->N0 = (uint32_t)N0;
+            a->m = m;
+            a->me = T.me;
+            a->mprev = mprev;
+            a->folds = folds;
+            a->R0prev = R0prev;
+            a->R0 = T.R0;
+            a->ncoll = T.ncoll;
+            a->sum_R = 0;
+            a->max_C = 0;
+            a->coff_max = 0;
+            for (uint32_t l = 1; l <= T.me; ++l) {
+                a->sum_R += T.R[l];
+                if (T.C[l] > a->max_C) a->max_C = T.C[l];
+                const uint64_t co = (reuse ? cprev[l] : 0) + T.C[l];
+                if (co > a->coff_max) a->coff_max = co;
+            }
+            a->borrowed = ro.borrowed;
+            a->n_th = ro.n_th;
+        }
 
         /* Tree-shape truncation (reading R15): finals whose tree is longer than
          * m_max are thermalized; the decision needs the schedule only. */

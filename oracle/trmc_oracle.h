@@ -38,6 +38,20 @@ typedef struct {
     double q, g, E1;
 } orc_cell_record;
 
+/* Integer outline of one attempt of a cell's step (after its folds), recorded
+ * while a log is set on the calling thread: what a kernel's index arithmetic
+ * has to hold.  sum_R = sum of the requests over levels 1..me; max_C = most
+ * collisions of one level; coff_max = largest draw offset of a level after the
+ * attempt (reuse). */
+typedef struct {
+    uint32_t n, N0, m, me, mprev, folds;
+    uint64_t R0prev, R0, ncoll, sum_R, max_C, coff_max, borrowed, n_th;
+} orc_attempt;
+
+/* Record the attempts of the cell steps this thread runs into buf (at most cap;
+ * NULL stops recording); returns the number recorded since the last call. */
+uint64_t orc_attempt_log(orc_attempt* buf, uint64_t cap);
+
 void orc_philox(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]);
 double orc_exp_neg(double x);
 double orc_grid_up(double g);
