@@ -246,6 +246,7 @@ struct CellShared {
     uint32_t ext_empty;  // the split continued past depth m would leave every level up to m_cap empty
     unsigned long long ncoll, work;
     uint32_t dummies, viol;
+    double fc[3], ft[8];  // a cell predicted wholly thermalized: centre and sums of its moments pass
 };
 
 // Level arrays of a group, lv_stride = m_cap + 2 entries each (dynamic LDS).

@@ -81,6 +81,10 @@ constexpr bool kMajBracket = TRMC_MAJ_BRACKET != 0;  // the majorant bracket of 
 #define TRMC_LAZY_ROLES 1
 #endif
 constexpr bool kLazyRoles = TRMC_LAZY_ROLES != 0;  // roles made after the split for cells predicted all-thermalized
+#ifndef TRMC_FAST_THERMAL
+#define TRMC_FAST_THERMAL 1
+#endif
+constexpr bool kFastThermal = TRMC_FAST_THERMAL != 0 && kLazyRoles;  // sums of wholly thermalized cells in the moments pass
 constexpr int kUnroll = TRMC_SLOT_UNROLL;  // slots per thread per batch in the moment and normal passes
 
 // One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
@@ -145,8 +149,8 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     // A cell whose previous step thermalized every particle (small eps) most
     // likely does so again: its roles are not made up front.  An attempt that
     // keeps or collides any particle makes them after its split; while none
-    // has, every slot is thermalized and the slot passes read no roles.  The
-    // sums are the same either way (same slots, same order).
+    // has, every slot is thermalized and the slot passes read no roles (they
+    // visit the same slots in the same order as with roles).
     bool roles_ready = true;
     if constexpr (kLazyRoles && !WB && !REUSE) {
         // the cell's record of its last step (this group's own previous step in a
@@ -154,6 +158,15 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         const bool all_th = st->n == n && st->N0 == 0u && st->n_th == n && st->status == 0u;
         roles_ready = !uni((uint32_t)all_th);
     }
+
+    // Such a cell also sums, in the moments pass, its velocities about the
+    // previous step's mean fc (sum of v - fc, of |v - fc|^2) and the Maxwellian
+    // normals of its slots (sum of z, of |z|^2): when its attempt does thermalize
+    // every particle, the removed set's sums and the normals' sums are at hand,
+    // and the gather and the normal pass are not made (two passes over the
+    // slots instead of four).  The two means differ by rounding only, so the
+    // one-pass energy about fc loses nothing.
+    const bool fast = kFastThermal && !roles_ready;
 
     TRMC_PHASE_BEGIN();
     // ---- 1-2. moments, roles, parameters of the step ------------------------
@@ -167,6 +180,13 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         // the two means differ by rounding only.
         const bool bk = kMajBracket && !DYN && G > 64 && uni((uint64_t)__double_as_longlong(I->alpha)) != 0ull;
         double bc0 = 0.0, bc1 = 0.0, bc2 = 0.0, d2c = 0.0;
+        double fc0 = 0.0, fc1 = 0.0, fc2 = 0.0;
+        double ft[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // this thread's fast sums, then the group's (kept in sh)
+        if (fast) {
+            fc0 = soff > 0 ? sh.mean[0] : st->mean[0];
+            fc1 = soff > 0 ? sh.mean[1] : st->mean[1];
+            fc2 = soff > 0 ? sh.mean[2] : st->mean[2];
+        }
         if (bk) {
             bc0 = soff > 0 ? sh.mean[0] : st->mean[0];
             bc1 = soff > 0 ? sh.mean[1] : st->mean[1];
@@ -207,6 +227,19 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                         const double e2 = ex * ex + ey * ey + ez * ez;
                         d2c = e2 > d2c ? e2 : d2c;
                     }
+                    if (fast) {
+                        const double ex = (double)ax[u] - fc0, ey = (double)ay[u] - fc1, ez = (double)az[u] - fc2;
+                        ft[0] += ex;
+                        ft[1] += ey;
+                        ft[2] += ez;
+                        ft[3] += ex * ex + ey * ey + ez * ez;
+                        const Vec3<T> z = Draws<T>::normals(key, i);  // keyed by the slot
+                        const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
+                        ft[4] += zx;
+                        ft[5] += zy;
+                        ft[6] += zz;
+                        ft[7] += zx * zx + zy * zy + zz * zz;
+                    }
                 }
             }
 #pragma unroll
@@ -218,6 +251,16 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         }
         if (roles_ready) make_roles();
         gsum<G, 4>(s, gl.red);
+        if (fast) {
+            gsum<G, 8>(ft, gl.red);
+            if (tid == 0) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sh.ft[q] = ft[q];
+                sh.fc[0] = fc0;
+                sh.fc[1] = fc1;
+                sh.fc[2] = fc2;
+            }
+        }
         const double inv = 1.0 / (double)n;
         const double dxm = s[0] * inv;
         const double mx = c0 + dxm, my = s[1] * inv, mz = s[2] * inv;
@@ -345,8 +388,18 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
             if (tid == 0) sums[0] = sh.kept0;
         } else {
             // (an attempt without roles keeps no pool: its slots' ranks are not known)
-            const bool pool_all = attempt > 0 && no_borrow && roles_ready;
-            if (roles_ready)
+            const bool pool_all = attempt > 0 && no_borrow && roles_ready && !(fast && leaf_end == 0u);
+            if (fast && leaf_end == 0u) {
+                // every slot thermalized: its sums about the mean from those about fc
+                if (tid == 0) {
+                    const double* ft = sh.ft;
+                    const double nd = (double)n, d0 = mx - sh.fc[0], d1 = my - sh.fc[1], d2 = mz - sh.fc[2];
+                    sums[2] = ft[0] - nd * d0;
+                    sums[3] = ft[1] - nd * d1;
+                    sums[4] = ft[2] - nd * d2;
+                    sums[5] = ft[3] - 2.0 * (d0 * ft[0] + d1 * ft[1] + d2 * ft[2]) + nd * (d0 * d0 + d1 * d1 + d2 * d2);
+                }
+            } else if (roles_ready)
                 gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done,
                                   pool_all, mx, my, mz, tid, sums);
             else
@@ -484,9 +537,11 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     if (!WB && thermalize) {
         // sums of the normals of the thermalized slots (keyed by the slot); the
         // write-back draws the same normals again and rescales them (cheaper
-        // than storing and reloading them)
+        // than storing and reloading them).  A cell whose moments pass summed
+        // them (every slot thermalized) has them already.
+        const bool zready = fast && leaf_end == 0u;
         double zs[4] = {0, 0, 0, 0};
-        for (uint32_t s0 = tid; s0 < n; s0 += G * kUnroll) {
+        for (uint32_t s0 = tid; !zready && s0 < n; s0 += G * kUnroll) {
             uint32_t ro[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -506,7 +561,12 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                 }
             }
         }
-        gsum<G, 4>(zs, gl.red);
+        if (zready) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) zs[q] = sh.ft[4 + q];  // (read by thread 0 only)
+        } else {
+            gsum<G, 4>(zs, gl.red);
+        }
         if (tid == 0) {
             const double nt = (double)n_th;
             const double zb0 = zs[0] / nt, zb1 = zs[1] / nt, zb2 = zs[2] / nt;
