@@ -6,6 +6,9 @@ log-uniform in [1e-4, 10], Maxwell molecules and hard spheres alternating, BKW
 or bi-Maxwellian initial data, dt = 0.05, adaptive depth (m_init 2, m_cap 64,
 delta1 0.005, delta2 0.01).  A step is one collision step of every instance; the
 metric is particle-steps per second over the timed steps (state resident in HBM).
+By default 20 untimed steps come first: over them the adaptive depths settle (the
+first steps redo many attempts) and the launch order learns each cell's cost, so
+the 20 timed steps are the solver's steady regime.
 
 The headline (value, roofline) is measured first.  Then, by default, the legs
 cpu (the oracle on host threads), batching (batched against one instance at a
@@ -584,7 +587,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
