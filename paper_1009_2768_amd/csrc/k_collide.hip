@@ -85,6 +85,10 @@ constexpr bool kLazyRoles = TRMC_LAZY_ROLES != 0;  // roles made after the split
 #define TRMC_FAST_THERMAL 1
 #endif
 constexpr bool kFastThermal = TRMC_FAST_THERMAL != 0 && kLazyRoles;  // sums of wholly thermalized cells in the moments pass
+#ifndef TRMC_PREFETCH_ROLES
+#define TRMC_PREFETCH_ROLES 1
+#endif
+constexpr bool kPrefetchRoles = TRMC_PREFETCH_ROLES != 0;  // next batch's roles loaded ahead in the slot passes
 constexpr int kUnroll = TRMC_SLOT_UNROLL;  // slots per thread per batch in the moment and normal passes
 
 // One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
@@ -541,12 +545,25 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         // them (every slot thermalized) has them already.
         const bool zready = fast && leaf_end == 0u;
         double zs[4] = {0, 0, 0, 0};
+        // the next batch's roles are loaded while this batch's normals are drawn
+        uint32_t rz[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t i = tid + u * G;
+            rz[u] = (kPrefetchRoles && !zready && i < n) ? (roles_ready ? M.role[i] : leaf_end) : 0u;
+        }
         for (uint32_t s0 = tid; !zready && s0 < n; s0 += G * kUnroll) {
             uint32_t ro[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t i = s0 + u * G;
-                ro[u] = i < n ? (roles_ready ? M.role[i] : leaf_end) : 0u;
+                if constexpr (kPrefetchRoles) {
+                    ro[u] = rz[u];
+                    const uint32_t j = i + G * kUnroll;
+                    rz[u] = j < n ? (roles_ready ? M.role[j] : leaf_end) : 0u;
+                } else {
+                    ro[u] = i < n ? (roles_ready ? M.role[i] : leaf_end) : 0u;
+                }
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -587,13 +604,26 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         constexpr int kWU = TRMC_WRITE_UNROLL;
         // the roles of a batch, then the finals of its leaf slots (final r of
         // leaf r); thermalized slots draw their normals again
+        // the next batch's roles are loaded while this batch is written
+        uint32_t rw[kWU];
+#pragma unroll
+        for (int u = 0; u < kWU; ++u) {
+            const uint32_t s = tid + u * G;
+            rw[u] = (kPrefetchRoles && s < n) ? (roles_ready ? M.role[s] : leaf_end) : 0u;
+        }
         for (uint32_t s0 = tid; s0 < n; s0 += G * kWU) {
             uint32_t ro[kWU];
             T fx[kWU], fy[kWU], fz[kWU];
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {
                 const uint32_t s = s0 + u * G;
-                ro[u] = s < n ? (roles_ready ? M.role[s] : leaf_end) : 0u;
+                if constexpr (kPrefetchRoles) {
+                    ro[u] = rw[u];
+                    const uint32_t j = s + G * kWU;
+                    rw[u] = j < n ? (roles_ready ? M.role[j] : leaf_end) : 0u;
+                } else {
+                    ro[u] = s < n ? (roles_ready ? M.role[s] : leaf_end) : 0u;
+                }
             }
 #pragma unroll
             for (int u = 0; u < kWU; ++u) {
