@@ -323,9 +323,9 @@ __device__ __forceinline__ void st3(gptr<Pack4<T>> p, T x, T y, T z)
     p->w = T(0);
 }
 
-template <typename T>
+template <typename T, typename R = uint32_t>
 struct CellMem {
-    gptr<uint32_t> role;  // [n] role index of each slot (inverse of the keyed permutation)
+    gptr<R> role;         // [n] role index of each slot (inverse of the keyed permutation)
     gptr<uint32_t> fwd;   // [n] slot of each role index (the permutation itself; tile path)
     gptr<Pack4<T>> leaf;  // [n] leaves by leaf rank (whole-cell path)
     gptr<Pack4<T>> fin;   // [n] finals by leaf rank (final r goes to the slot of leaf r)
@@ -340,8 +340,8 @@ struct CellMem {
         ocap = 2ull * cap;
         // the cell is the same on every lane of the wave: scalar base pointers
         unsigned char* base = uni(I->scratch + I->scratch_bpp * (uint64_t)off + I->scratch_cpc * (uint64_t)cell);
-        role = as_global(reinterpret_cast<uint32_t*>(base));
-        base += align16(4ull * n);
+        role = as_global(reinterpret_cast<R*>(base));
+        base += align16(4ull * n);  // room for 32-bit roles either way
         fwd = as_global(reinterpret_cast<uint32_t*>(base));
         base += align16(4ull * n);
         leaf = as_global(reinterpret_cast<Pack4<T>*>(base));
@@ -747,9 +747,9 @@ __device__ __forceinline__ uint32_t leaf_role(uint32_t r, uint32_t N0, uint32_t 
 // are unchanged, roles from leaf_end on are thermalized, the others are leaves.
 // ALL_TH: an attempt with no unchanged slots and no leaves (kept_end = leaf_end
 // = 0), whose roles are not read: every slot is thermalized.
-template <typename T, int NT, bool ALL_TH = false>
+template <typename T, int NT, bool ALL_TH = false, typename R = uint32_t>
 __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, gptr<const T> vz,
-                                            gptr<const uint32_t> role, gptr<Pack4<T>> leaf,
+                                            gptr<const R> role, gptr<Pack4<T>> leaf,
                                             uint32_t n, uint32_t N0, uint32_t s_begin, uint32_t s_end,
                                             uint32_t kept_end, uint32_t leaf_end, uint32_t r_done, bool pool_all,
                                             double mx, double my, double mz, uint32_t tid, double (&sums)[6])
@@ -766,7 +766,7 @@ __device__ __forceinline__ void gather_sets(gptr<const T> vx, gptr<const T> vy, 
         for (int u = 0; u < U; ++u) {
             const uint32_t i = s0 + u * NT;
             const bool ok = i < s_end;
-            ro[u] = ok ? (ALL_TH ? leaf_end : role[i]) : 0xFFFFFFFFu;
+            ro[u] = ok ? (ALL_TH ? leaf_end : (uint32_t)role[i]) : 0xFFFFFFFFu;
             ax[u] = ok ? vx[i] : T(0);
             ay[u] = ok ? vy[i] : T(0);
             az[u] = ok ? vz[i] : T(0);
@@ -821,10 +821,10 @@ struct WbAcc {
     double z[4], d[4], cnt;
 };
 
-template <typename T, int G, bool FromSlots, bool WB = false, bool REUSE = false>
+template <typename T, int G, bool FromSlots, bool WB = false, bool REUSE = false, typename R = uint32_t>
 __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const T> vx, gptr<const T> vy,
                                           gptr<const T> vz,
-                                          const Levels& L, const CellShared& sh, const CellMem<T>& M,
+                                          const Levels& L, const CellShared& sh, const CellMem<T, R>& M,
                                           unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
                                           uint32_t& dummies, uint32_t& viol, double& sfin, uint32_t wbk = 0,
                                           const uint32_t* coff = nullptr, uint32_t r0prev = 0,

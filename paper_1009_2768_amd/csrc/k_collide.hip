@@ -89,18 +89,33 @@ constexpr bool kFastThermal = TRMC_FAST_THERMAL != 0 && kLazyRoles;  // sums of 
 #define TRMC_PREFETCH_ROLES 1
 #endif
 constexpr bool kPrefetchRoles = TRMC_PREFETCH_ROLES != 0;  // next batch's roles loaded ahead in the slot passes
+#ifndef TRMC_ROLES16
+#define TRMC_ROLES16 1
+#endif
+constexpr bool kRoles16 = TRMC_ROLES16 != 0;  // 16-bit roles for cells of at most 65536 particles
 constexpr int kUnroll = TRMC_SLOT_UNROLL;  // slots per thread per batch in the moment and normal passes
+
+// LDS of the groups of a whole-cell workgroup (one group of the workgroup's
+// size, or one per wave), shared by every instance of the step function: a
+// workgroup runs one kind of group, each group one cell, one step at a time.
+// One buffer instead of one per instance keeps the static LDS of the kernel to
+// the largest kind.
+constexpr size_t kGroupLdsBytes = sizeof(GroupLds<kCollideThreads>) > kSmallPerBlock * sizeof(GroupLds<64>)
+                                      ? sizeof(GroupLds<kCollideThreads>)
+                                      : kSmallPerBlock * sizeof(GroupLds<64>);
+__shared__ __attribute__((aligned(16))) unsigned char g_group_lds[kGroupLdsBytes];
 
 // One step of the cell of group blk / NGRP.  Kept out of line: the kernels call
 // it once per step, and inlined into their step loops the compiler keeps
 // per-step values live across the whole loop and spills them.
-template <typename T, int NT, int G, bool WB = false, bool REUSE = false, bool DYN = false>
+template <typename T, int NT, int G, bool WB = false, bool REUSE = false, bool DYN = false, typename R = uint32_t>
 __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restrict__ work, uint32_t n_work, uint32_t blk,
                                               uint32_t lv_stride, uint32_t soff)
 {
     constexpr int NGRP = NT / G;  // groups per workgroup
+    static_assert(NGRP * sizeof(GroupLds<G>) <= kGroupLdsBytes, "group LDS exceeds the shared buffer");
     extern __shared__ uint32_t lds_levels[];
-    __shared__ GroupLds<G> glds[NGRP];
+    GroupLds<G>* const glds = reinterpret_cast<GroupLds<G>*>(g_group_lds);
 
     const uint32_t grp = uni((uint32_t)(threadIdx.x / G));
     const uint32_t wi = blk * NGRP + grp;
@@ -135,7 +150,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         }
         return;
     }
-    CellMem<T> M;
+    CellMem<T, R> M;
     M.init(I, off, cell, n);
     Levels L = levels_at(lds_levels + (size_t)grp * 5u * lv_stride, lv_stride);
 
@@ -404,11 +419,11 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                     sums[5] = ft[3] - 2.0 * (d0 * ft[0] + d1 * ft[1] + d2 * ft[2]) + nd * (d0 * d0 + d1 * d1 + d2 * d2);
                 }
             } else if (roles_ready)
-                gather_sets<T, G>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done,
-                                  pool_all, mx, my, mz, tid, sums);
+                gather_sets<T, G, false, R>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end,
+                                            leaves_done, pool_all, mx, my, mz, tid, sums);
             else
-                gather_sets<T, G, true>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end, leaves_done,
-                                        pool_all, mx, my, mz, tid, sums);
+                gather_sets<T, G, true, R>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end,
+                                           leaves_done, pool_all, mx, my, mz, tid, sums);
             leaves_done = pool_all ? P : (R0 > leaves_done ? R0 : leaves_done);
             pooled = pool_all;
         }
@@ -422,7 +437,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         // the majorant raised level by level (Remark 4.1), from the step's bound
         DynMajorant dmj{gl.red, I->alpha, sh.d2max0, sh.g};
         const bool dyn = DYN && I->alpha != 0.0;
-        bottom_up<T, G, false, WB, REUSE>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol,
+        bottom_up<T, G, false, WB, REUSE, R>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol,
                                           sfin, WB ? uni(I->wb) : 0u, coff, r0prev, &wba,
                                           WB ? (T)uni(I->wb_mmax) : T(0), dyn ? &dmj : nullptr);
         if (tid == 0) sh.g_last = dmj.g;
@@ -663,6 +678,14 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
     if (tid == 0) write_stats(st, n, sh, elapsed_ticks(t_begin));
 }
 
+// Particles of a work item's cell (wave-uniform).
+__device__ __forceinline__ uint32_t cell_size(const CellRef& r)
+{
+    const InstDev* I = uni(r.inst);
+    const uint32_t c = uni(r.cell);
+    return uni(I->cell_off[c + 1]) - uni(I->cell_off[c]);
+}
+
 // Groups of eight wave-per-cell cells occupy the first workgroups, cells of the
 // workgroup-per-cell list the rest: the dispatcher starts workgroups in index
 // order, and the few small-cell groups, whose deep trees make their waves run
@@ -693,6 +716,9 @@ __device__ __forceinline__ void collide_entry(const CellRef* __restrict__ big, u
             const uint32_t bb = b - small_blocks;
             if (!REUSE && uni(big[bb].inst->majorant) == MAJ_LEVEL)
                 collide_cells<T, kCollideThreads, kCollideThreads, false, false, true>(big, n_big, bb, lv_big, s);
+            else if (!REUSE && kRoles16 && bb < n_big && cell_size(big[bb]) <= 65536u)
+                collide_cells<T, kCollideThreads, kCollideThreads, false, false, false, uint16_t>(big, n_big, bb,
+                                                                                                 lv_big, s);
             else
                 collide_cells<T, kCollideThreads, kCollideThreads, false, REUSE>(big, n_big, bb, lv_big, s);
             gsync<kCollideThreads>();
@@ -700,6 +726,8 @@ __device__ __forceinline__ void collide_entry(const CellRef* __restrict__ big, u
             const uint32_t wi = b * kSmallPerBlock + uni((uint32_t)(threadIdx.x / 64));
             if (!REUSE && wi < n_small && uni(small[wi].inst->majorant) == MAJ_LEVEL)
                 collide_cells<T, kCollideThreads, 64, false, false, true>(small, n_small, b, lv_small, s);
+            else if (!REUSE && kRoles16 && wi < n_small && cell_size(small[wi]) <= 65536u)
+                collide_cells<T, kCollideThreads, 64, false, false, false, uint16_t>(small, n_small, b, lv_small, s);
             else
                 collide_cells<T, kCollideThreads, 64, false, REUSE>(small, n_small, b, lv_small, s);
             gsync<64>();

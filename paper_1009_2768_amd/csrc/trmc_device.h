@@ -208,8 +208,10 @@ __device__ __forceinline__ uint32_t perm_inverse(uint32_t s, uint32_t n, uint32_
 // Role index of every slot in [r0, r1) of a cell, written to role[], by one
 // wave whose lanes take the next slot as soon as their cycle walk ends: a wave
 // evaluates about (sum of the walks) / 64 rounds of the network instead of the
-// longest walk of its 64 slots per batch of 64.
-__device__ __forceinline__ void roles_by_wave(__attribute__((address_space(1))) uint32_t* role, uint32_t r0,
+// longest walk of its 64 slots per batch of 64.  R: the role's element type
+// (16 bits for cells of at most 65536 particles).
+template <typename R = uint32_t>
+__device__ __forceinline__ void roles_by_wave(__attribute__((address_space(1))) R* role, uint32_t r0,
                                               uint32_t r1, uint32_t n, uint32_t b, uint4 k)
 {
     const uint32_t lane = __lane_id();
@@ -228,7 +230,7 @@ __device__ __forceinline__ void roles_by_wave(__attribute__((address_space(1))) 
         if (cur != 0xFFFFFFFFu) {
             val = feistel_dec(val, b, k);
             if (val < n) {
-                role[cur] = val;
+                role[cur] = (R)val;
                 cur = 0xFFFFFFFFu;
             }
         }
