@@ -246,7 +246,8 @@ struct CellShared {
     uint32_t ext_empty;  // the split continued past depth m would leave every level up to m_cap empty
     unsigned long long ncoll, work;
     uint32_t dummies, viol;
-    double fc[3], ft[8];  // a cell predicted wholly thermalized: centre and sums of its moments pass
+    double all_th[4];  // the whole cell about its mean: sum of v - m (3), of |v - m|^2 (moments pass)
+    double zt[4];      // a cell predicted wholly thermalized: its normals' sums (moments pass)
 };
 
 // Level arrays of a group, lv_stride = m_cap + 2 entries each (dynamic LDS).

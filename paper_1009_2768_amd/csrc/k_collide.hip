@@ -178,20 +178,23 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         roles_ready = !uni((uint32_t)all_th);
     }
 
-    // Such a cell also sums, in the moments pass, its velocities about the
-    // previous step's mean fc (sum of v - fc, of |v - fc|^2) and the Maxwellian
-    // normals of its slots (sum of z, of |z|^2): when its attempt does thermalize
-    // every particle, the removed set's sums and the normals' sums are at hand,
-    // and the gather and the normal pass are not made (two passes over the
-    // slots instead of four).  The two means differ by rounding only, so the
-    // one-pass energy about fc loses nothing.
+    // Such a cell also sums, in the moments pass, the Maxwellian normals of its
+    // slots (sum of z, of |z|^2; the same slots in the same order as the normal
+    // pass): when its attempt does thermalize every particle, the normal pass is
+    // not made.  Every cell's moments pass sums its velocities about the first
+    // particle's (c), so that an attempt that thermalizes every particle takes
+    // the removed set's sums from there instead of a gather pass; together,
+    // two passes over the slots instead of four.  None of this depends on the
+    // prediction: only whether the normals are summed early does.
     const bool fast = kFastThermal && !roles_ready;
 
     TRMC_PHASE_BEGIN();
     // ---- 1-2. moments, roles, parameters of the step ------------------------
     {
         const double c0 = (double)vx[0];  // shift for the one-pass P_xx
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        const double c1 = (double)vy[0], c2 = (double)vz[0];
+        // sums of v_x - c0, v_y, v_z, (v_x - c0)^2, (v_y - c1)^2, (v_z - c2)^2
+        double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         // VHS cells of a workgroup: the largest distance to the previous step's
         // mean (this group's last step of the cell, else the cell's record from
         // the last launch) brackets the majorant; the exact pass below runs only
@@ -199,13 +202,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         // the two means differ by rounding only.
         const bool bk = kMajBracket && !DYN && G > 64 && uni((uint64_t)__double_as_longlong(I->alpha)) != 0ull;
         double bc0 = 0.0, bc1 = 0.0, bc2 = 0.0, d2c = 0.0;
-        double fc0 = 0.0, fc1 = 0.0, fc2 = 0.0;
-        double ft[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // this thread's fast sums, then the group's (kept in sh)
-        if (fast) {
-            fc0 = soff > 0 ? sh.mean[0] : st->mean[0];
-            fc1 = soff > 0 ? sh.mean[1] : st->mean[1];
-            fc2 = soff > 0 ? sh.mean[2] : st->mean[2];
-        }
+        double zt[4] = {0, 0, 0, 0};  // this thread's sums of the normals (fast), then the group's
         if (bk) {
             bc0 = soff > 0 ? sh.mean[0] : st->mean[0];
             bc1 = soff > 0 ? sh.mean[1] : st->mean[1];
@@ -241,23 +238,21 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                     s[1] += (double)ay[u];
                     s[2] += (double)az[u];
                     s[3] += dx * dx;
+                    const double dy = (double)ay[u] - c1, dz = (double)az[u] - c2;
+                    s[4] += dy * dy;
+                    s[5] += dz * dz;
                     if (bk) {
                         const double ex = (double)ax[u] - bc0, ey = (double)ay[u] - bc1, ez = (double)az[u] - bc2;
                         const double e2 = ex * ex + ey * ey + ez * ez;
                         d2c = e2 > d2c ? e2 : d2c;
                     }
                     if (fast) {
-                        const double ex = (double)ax[u] - fc0, ey = (double)ay[u] - fc1, ez = (double)az[u] - fc2;
-                        ft[0] += ex;
-                        ft[1] += ey;
-                        ft[2] += ez;
-                        ft[3] += ex * ex + ey * ey + ez * ez;
                         const Vec3<T> z = Draws<T>::normals(key, i);  // keyed by the slot
                         const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
-                        ft[4] += zx;
-                        ft[5] += zy;
-                        ft[6] += zz;
-                        ft[7] += zx * zx + zy * zy + zz * zz;
+                        zt[0] += zx;
+                        zt[1] += zy;
+                        zt[2] += zz;
+                        zt[3] += zx * zx + zy * zy + zz * zz;
                     }
                 }
             }
@@ -269,20 +264,26 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
             }
         }
         if (roles_ready) make_roles();
-        gsum<G, 4>(s, gl.red);
+        gsum<G, 6>(s, gl.red);
         if (fast) {
-            gsum<G, 8>(ft, gl.red);
+            gsum<G, 4>(zt, gl.red);
             if (tid == 0) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) sh.ft[q] = ft[q];
-                sh.fc[0] = fc0;
-                sh.fc[1] = fc1;
-                sh.fc[2] = fc2;
+                for (int q = 0; q < 4; ++q) sh.zt[q] = zt[q];
             }
         }
         const double inv = 1.0 / (double)n;
         const double dxm = s[0] * inv;
         const double mx = c0 + dxm, my = s[1] * inv, mz = s[2] * inv;
+        if (tid == 0) {
+            // the sums of the whole cell about its mean, for an attempt that
+            // thermalizes every particle: sum of v - m (rounding only) and of |v - m|^2
+            const double nd = (double)n, ey = my - c1, ez = mz - c2;
+            sh.all_th[0] = s[0] - nd * dxm;
+            sh.all_th[1] = s[1] - nd * my;
+            sh.all_th[2] = s[2] - nd * mz;
+            sh.all_th[3] = (s[3] - nd * dxm * dxm) + (s[4] - nd * ey * ey) + (s[5] - nd * ez * ez);
+        }
         double dmax = 0.0;
         if (bk) {
             // every thread reduces the same values in the same order: a uniform verdict
@@ -407,16 +408,15 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
             if (tid == 0) sums[0] = sh.kept0;
         } else {
             // (an attempt without roles keeps no pool: its slots' ranks are not known)
-            const bool pool_all = attempt > 0 && no_borrow && roles_ready && !(fast && leaf_end == 0u);
-            if (fast && leaf_end == 0u) {
-                // every slot thermalized: its sums about the mean from those about fc
+            const bool whole = kFastThermal && !WB && !REUSE && leaf_end == 0u;
+            const bool pool_all = attempt > 0 && no_borrow && roles_ready && !whole;
+            if (whole) {
+                // every slot thermalized: the whole cell's sums from the moments pass
                 if (tid == 0) {
-                    const double* ft = sh.ft;
-                    const double nd = (double)n, d0 = mx - sh.fc[0], d1 = my - sh.fc[1], d2 = mz - sh.fc[2];
-                    sums[2] = ft[0] - nd * d0;
-                    sums[3] = ft[1] - nd * d1;
-                    sums[4] = ft[2] - nd * d2;
-                    sums[5] = ft[3] - 2.0 * (d0 * ft[0] + d1 * ft[1] + d2 * ft[2]) + nd * (d0 * d0 + d1 * d1 + d2 * d2);
+                    sums[2] = sh.all_th[0];
+                    sums[3] = sh.all_th[1];
+                    sums[4] = sh.all_th[2];
+                    sums[5] = sh.all_th[3];
                 }
             } else if (roles_ready)
                 gather_sets<T, G, false, R>(vx, vy, vz, M.role, M.leaf, n, N0, 0u, n, kept_end, leaf_end,
@@ -595,7 +595,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         }
         if (zready) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) zs[q] = sh.ft[4 + q];  // (read by thread 0 only)
+            for (int q = 0; q < 4; ++q) zs[q] = sh.zt[q];  // (read by thread 0 only)
         } else {
             gsum<G, 4>(zs, gl.red);
         }

@@ -93,3 +93,44 @@ def test_roles_when_needed_match_oracle(trmc, orc, kind, path, trunc):
     ctx.close()
     for c in ("vx", "vy", "vz"):
         assert np.array_equal(fused[c], single[c]), c
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_restart_through_the_shortcuts_is_bitwise(trmc, prec):
+    """A run restarted from its saved state (step index, adaptive depths) equals
+    the uninterrupted run bitwise, also where the step's shortcuts apply (roles
+    made only when needed, the whole cell's sums from the moments pass, the
+    normals summed early, the majorant from its bracket), which a restarted
+    context takes from a blank record."""
+    T = trmc
+    P = T.FP64 if prec == "fp64" else T.FP32_MIXED
+    say("restart through the shortcuts", prec)
+    specs = [(3000, 1e-4, 0.0), (2000, 0.05 / math.log(100.0 * 2000), 0.0), (6000, 0.01, 1.0), (300, 1e-4, 1.0),
+             (4000, 0.2, 1.0)]
+    insts, arrs = [], []
+    for k, (n, eps, alpha) in enumerate(specs):
+        v = W.bkw(n, 0.6, 0, 500 + k) if k % 2 == 0 else W.bimaxwellian(n, 0, 500 + k)
+        insts.append(dict(n_particles=n, eps=eps, alpha=alpha, trunc=T.ADAPTIVE, m_init=2, m_cap=64, uid=60 + k,
+                          seed=9, dt=0.05, precision=P, particle_weight=1.0 / n))
+        arrs.append(v)
+
+    def ctx_of(kw_list, arr_list):
+        return T.Context([T.Instance(**kw) for kw in kw_list],
+                         [T.device_particles(*a, precision=P) for a in arr_list])
+
+    ctx = ctx_of(insts, arrs)
+    ctx.step(8)
+    full = [ctx.read(k) for k in range(len(insts))]
+    ctx.close()
+    ctx = ctx_of(insts, arrs)
+    ctx.step(4)
+    mid = [ctx.read(k) for k in range(len(insts))]
+    ctx.close()
+    again = [dict(kw, step0=4, m_state0=m["m_state"]) for kw, m in zip(insts, mid)]
+    ctx = ctx_of(again, [(m["vx"], m["vy"], m["vz"]) for m in mid])
+    ctx.step(4)
+    out = [ctx.read(k) for k in range(len(insts))]
+    ctx.close()
+    for k in range(len(insts)):
+        for c in ("vx", "vy", "vz"):
+            assert np.array_equal(full[k][c], out[k][c]), (k, c)
