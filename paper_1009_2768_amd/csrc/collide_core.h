@@ -829,7 +829,8 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
                                           unsigned long long ncoll, T alpha, T gT, double mx, uint32_t tid,
                                           uint32_t& dummies, uint32_t& viol, double& sfin, uint32_t wbk = 0,
                                           const uint32_t* coff = nullptr, uint32_t r0prev = 0,
-                                          WbAcc* wba = nullptr, T wbmax = T(0), DynMajorant* dm = nullptr)
+                                          WbAcc* wba = nullptr, T wbmax = T(0), DynMajorant* dm = nullptr,
+                                          uint32_t l_first = 1)
 {
     const uint32_t N0 = uni(sh.N0), P = n - N0, me = uni(sh.me);
     // tree-shape truncation: a dropped final's slot is the permutation of its
@@ -847,6 +848,12 @@ __device__ __forceinline__ void bottom_up(const Key& key, uint32_t n, gptr<const
     for (uint32_t l = 1; l <= me; ++l) {
         const uint32_t Cl = uni(L.C[l]), Rl = uni(L.Rtot[l]);
         if (Cl == 0) continue;
+        if (l < l_first) {
+            // made elsewhere (the tile pipeline's level-1 kernel): only the offsets move on
+            above -= Cl;
+            fp += 2u * Cl - Rl;
+            continue;
+        }
         above -= Cl;
         const uint32_t fst = (uint32_t)above;
         const uint32_t oo = uni(L.outoff[l]);

@@ -41,6 +41,17 @@ __device__ __forceinline__ uint32_t* big_levels(const InstDev* I)
 {
     return reinterpret_cast<uint32_t*>(I->bigstate + kBigStateBytes);
 }
+// level-1 partial sums of kLevel1Blocks workgroups: {finals' (vx - m)^2, dummies, violations, 0} each
+__device__ __forceinline__ double* big_parts(const InstDev* I)
+{
+    return reinterpret_cast<double*>(I->bigstate + kBigStateBytes + big_levels_bytes(I->m_cap));
+}
+// Level 1 of the first attempt is made by k_big_level1 (not for the majorant
+// raised level by level, whose bound comes from the levels in turn).
+__device__ __forceinline__ bool level1_apart(const InstDev* I)
+{
+    return !(I->majorant == MAJ_LEVEL && I->alpha != 0.0);
+}
 
 template <typename T>
 struct CellView {
@@ -317,6 +328,77 @@ __global__ __launch_bounds__(kTT) void k_big_tree(const CellRef* __restrict__ bi
     }
 }
 
+// Level 1 of a large cell's first attempt, spread over kLevel1Blocks workgroups
+// per cell (grid: cells x kLevel1Blocks).  Its collisions take two leaves each
+// and nothing from other collisions, so each workgroup takes a contiguous share;
+// outputs and finals go where the one-workgroup level loop puts them.  Each
+// workgroup's sums (finals' (vx - m)^2, dummies, violations) go to the cell's
+// partials, which k_big_collide adds in workgroup order.
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_big_level1(const CellRef* __restrict__ bigs, uint32_t nb, uint32_t lv_stride)
+{
+    __shared__ double red[(kTT / 64) * 12 + 12];
+    __shared__ uint32_t redu[(kTT / 64) * 2];
+    const uint32_t b = blockIdx.x / kLevel1Blocks, w = blockIdx.x % kLevel1Blocks;
+    if (b >= nb) return;
+    InstDev* I = bigs[b].inst;
+    const BigState* S = big_state(I);
+    double* part = big_parts(I) + 4ull * w;
+    const uint32_t* gL = big_levels(I);
+    const uint32_t n = I->cell_off[1] - I->cell_off[0];
+    const uint32_t tid = threadIdx.x;
+    const bool run = !S->sh.overflow && S->sh.me >= 1u && level1_apart(I);
+    const uint32_t Cl = run ? gL[2u * lv_stride + 1u] : 0u;
+    const uint32_t share = (Cl + kLevel1Blocks - 1u) / kLevel1Blocks;
+    const uint32_t c_begin = w * share < Cl ? w * share : Cl;
+    const uint32_t c_end = c_begin + share < Cl ? c_begin + share : Cl;
+    double sfin = 0.0;
+    uint32_t dummies = 0, viol = 0;
+    if (c_begin < c_end) {
+        const uint32_t Rl = gL[lv_stride + 1u], oo = gL[3u * lv_stride + 1u];
+        const uint32_t N0 = S->sh.N0, P = n - N0;
+        const uint32_t fst = (uint32_t)(S->ncoll - Cl);  // level 1's collisions come last
+        const double mx = S->sh.mean[0];
+        const T alpha = (T)I->alpha, gT = (T)S->sh.g;
+        const Key key{I->seed, I->uid, 0u, I->step};
+        const gptr<const T> vx = as_global(reinterpret_cast<const T*>(I->vx[0]));
+        const gptr<const T> vy = as_global(reinterpret_cast<const T*>(I->vy[0]));
+        const gptr<const T> vz = as_global(reinterpret_cast<const T*>(I->vz[0]));
+        CellMem<T> M;
+        M.init(I, 0, 0, n);
+        for (uint32_t c = c_begin + tid; c < c_end; c += kTT) {
+            const uint32_t id = fst + c;
+            const uint32_t sa = M.fwd[leaf_role(M.rA[id], N0, P)], sb = M.fwd[leaf_role(M.rB[id], N0, P)];
+            const Vec3<T> a{vx[sa], vy[sa], vz[sa]}, bb{vx[sb], vy[sb], vz[sb]};
+            T xi1, xi2, xacc;
+            Draws<T>::coll(key, 1u, c, xi1, xi2, xacc);
+            Vec3<T> out[2];
+            if (!collide<T>(a, bb, xi1, xi2, xacc, alpha, gT, out[0], out[1], viol)) dummies++;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const uint32_t o = 2u * c + (uint32_t)e;
+                if (o < Rl) {
+                    st4(M.outv + ((uint64_t)oo + o), out[e].x, out[e].y, out[e].z, T(0));
+                } else {
+                    st4(M.fin + (o - Rl), out[e].x, out[e].y, out[e].z, T(0));
+                    const double d = (double)out[e].x - mx;
+                    sfin += d * d;
+                }
+            }
+        }
+    }
+    double fs[1] = {sfin};
+    gsum<kTT, 1>(fs, red);
+    const uint32_t td = gsum_u32<kTT>(dummies, redu);
+    const uint32_t tv = gsum_u32<kTT>(viol, redu);
+    if (tid == 0) {
+        part[0] = fs[0];
+        part[1] = (double)td;
+        part[2] = (double)tv;
+        part[3] = 0.0;
+    }
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__ bigs, uint32_t lv_stride,
                                                      CellLists cl)
@@ -359,6 +441,7 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
     const T alpha = (T)I->alpha;
     const T gT = (T)sh.g;
     unsigned long long ncoll = S->ncoll;
+    bool first = true;  // the first attempt's level 1 was made by k_big_level1
     for (;;) {
         // sums of the unchanged and thermalized sets of this attempt
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
@@ -370,19 +453,30 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
         // the majorant raised level by level (Remark 4.1), from the step's bound
         DynMajorant dmj{gl.red, I->alpha, sh.d2max0, sh.g};
         const bool dyn = uni(I->majorant) == MAJ_LEVEL && I->alpha != 0.0;
+        const bool apart = first && level1_apart(I);
         bottom_up<T, G, true>(key, n, vx, vy, vz, L, sh, M, ncoll, alpha, gT, mx, tid, dummies, viol, sfin, 0u,
-                              nullptr, 0u, nullptr, T(0), dyn ? &dmj : nullptr);
+                              nullptr, 0u, nullptr, T(0), dyn ? &dmj : nullptr, apart ? 2u : 1u);
         if (tid == 0) sh.g_last = dmj.g;
         double fs[1] = {sfin};
         gsum<G, 1>(fs, gl.red);
-        const uint32_t td = gsum_u32<G>(dummies, gl.redu);
-        const uint32_t tv = gsum_u32<G>(viol, gl.redu);
+        uint32_t td = gsum_u32<G>(dummies, gl.redu);
+        uint32_t tv = gsum_u32<G>(viol, gl.redu);
         if (tid == 0) {
+            if (apart) {
+                // level 1's sums, in workgroup order
+                const double* part = big_parts(I);
+                for (uint32_t w = 0; w < kLevel1Blocks; ++w) {
+                    fs[0] += part[4u * w];
+                    td += (uint32_t)part[4u * w + 1u];
+                    tv += (uint32_t)part[4u * w + 2u];
+                }
+            }
             all[6] = fs[0];
             sh.dummies = td;
             sh.viol = tv;
             decide(I, 0, n, all, mx, my, mz, sh);
         }
+        first = false;
         gsync<G>();
         if (sh.decision) break;
         // redo at depth sh.m
@@ -513,6 +607,7 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
     template __global__ void k_big_split<T>(const CellRef*, uint32_t, uint32_t, CellLists);    \
     template __global__ void k_big_tree<T, 64>(const CellRef*, uint32_t, CellLists);           \
     template __global__ void k_big_tree<T, kTT>(const CellRef*, uint32_t, CellLists);          \
+    template __global__ void k_big_level1<T>(const CellRef*, uint32_t, uint32_t);               \
     template __global__ void k_big_collide<T, 64>(const CellRef*, uint32_t, CellLists);        \
     template __global__ void k_big_collide<T, kTT>(const CellRef*, uint32_t, CellLists);       \
     template __global__ void k_tile_zsum<T>(const CellRef*, const uint32_t*, uint32_t);        \

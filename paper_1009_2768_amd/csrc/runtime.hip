@@ -43,6 +43,8 @@ template <typename T>
 __global__ void k_big_split(const CellRef*, uint32_t, uint32_t, CellLists);
 template <typename T, int G>
 __global__ void k_big_tree(const CellRef*, uint32_t, CellLists);
+template <typename T>
+__global__ void k_big_level1(const CellRef*, uint32_t, uint32_t);
 template <typename T, int G>
 __global__ void k_big_collide(const CellRef*, uint32_t, CellLists);
 template <typename T>
@@ -99,7 +101,8 @@ Layout layout_of(const trmc_desc& d)
         // tiled pipeline of large homogeneous cells: tile sums, state and level arrays
         L.tpart = p; p += al(sizeof(double) * 8 * ((n + kTile - 1) / kTile));
         L.bsum = p;  p += al(sizeof(double) * 8 * ((n + kRoleBlock - 1) / kRoleBlock));
-        L.big = p;   p += al(kBigStateBytes + sizeof(uint32_t) * 5 * ((size_t)d.m_cap + 2));
+        // state, level arrays, and the level-1 partial sums of kLevel1Blocks workgroups
+        L.big = p;   p += al(kBigStateBytes + big_levels_bytes(d.m_cap) + sizeof(double) * 4 * kLevel1Blocks);
     }
     L.scratch = p;
     p += al(scratch_bpp((uint32_t)sz) * n + scratch_cpc((uint32_t)sz) * nc);
@@ -569,6 +572,7 @@ int launch_tiled(trmc_ctx* c, int k)
         hipLaunchKernelGGL(k_big_split<T>, dim3(wblocks), dim3(512), lds8, c->stream, bigs, nt, stride, cl);
         hipLaunchKernelGGL((k_big_tree<T, 64>), dim3(wblocks), dim3(512), lds8, c->stream, bigs, stride, cl);
         hipLaunchKernelGGL((k_big_tree<T, 512>), dim3(nt), dim3(512), lds1, c->stream, bigs, stride, cl);
+        hipLaunchKernelGGL(k_big_level1<T>, dim3(nt * kLevel1Blocks), dim3(512), 0, c->stream, bigs, nt, stride);
         hipLaunchKernelGGL((k_big_collide<T, 64>), dim3(wblocks), dim3(512), lds8, c->stream, bigs, stride, cl);
         hipLaunchKernelGGL((k_big_collide<T, 512>), dim3(nt), dim3(512), lds1, c->stream, bigs, stride, cl);
         hipLaunchKernelGGL(k_tile_zsum<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);

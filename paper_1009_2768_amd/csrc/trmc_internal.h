@@ -30,6 +30,9 @@ __host__ __device__ inline uint32_t sort_tile(uint32_t n_cells)
 }
 constexpr uint32_t kTile = 8192;         // slots per tile of the tiled collision pipeline
 constexpr uint32_t kBigStateBytes = 1024; // per-cell state of the tiled pipeline (before its level arrays)
+constexpr uint32_t kLevel1Blocks = 32;    // workgroups per large cell for the collisions of its level 1
+// bytes of a large cell's level arrays (5 x (m_cap + 2) u32), rounded up to 8
+__host__ __device__ inline uint64_t big_levels_bytes(uint32_t m_cap) { return (20ull * (m_cap + 2ull) + 7ull) & ~7ull; }
 constexpr uint32_t kRoleBlock = 512;     // roles per block sum of the tiled pipeline
 #ifndef TRMC_COLLIDE_THREADS
 #define TRMC_COLLIDE_THREADS 512
