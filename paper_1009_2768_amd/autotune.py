@@ -8,6 +8,12 @@ path the bucket's cells can take is timed on copies of that bucket's instances
 (a fresh copy per candidate, so every candidate steps the same states).  The
 result is a table for Context.set_schedule.  Results do not depend on the
 schedule, so tuning never changes what a run computes, only how fast.
+
+A mix whose buckets run together (the served form) is refined afterwards on the
+whole mix (refine_for_mix): timed bucket by bucket, a bucket of a few large cells
+looks as fast on one workgroup per cell as on the tile pipeline, but in the mix
+its long single-workgroup chains lengthen the step of every other request, while
+the tile pipeline spreads them over many workgroups on a stream of its own.
 """
 from __future__ import annotations
 
@@ -86,3 +92,51 @@ def autotune(instances, particles, warmup=1, steps=2, max_particles=8_000_000, m
                 + ", ".join(f"{['default', 'group', 'wave', 'tiled'][p]} {t:.3f} ms" for p, t in res.items())
                 + f" -> {['default', 'group', 'wave', 'tiled'][best]} ({time.perf_counter() - t0:.1f} s)")
     return table, timings
+
+
+def refine_for_mix(instances, particles, table, warmup=2, steps=2, margin=0.03, log=None):
+    """Coordinate descent of a schedule table on the whole mix: one context holds
+    copies of every instance; bucket by bucket (largest share of particles first)
+    each other path the bucket's cells can take replaces the current one when a
+    step of the whole mix is faster by more than `margin`.  Both tables of a
+    comparison are timed back to back on the same context (the schedule never
+    changes results, so the copies may be stepped under either).  Returns the
+    refined table."""
+    import torch
+    buckets: dict[int, list[int]] = {}
+    for k, inst in enumerate(instances):
+        buckets.setdefault(size_bucket(inst), []).append(k)
+    clones = [{k: (v.clone() if v is not None else None) for k, v in p.items()} for p in particles]
+    ctx = Context([replace(i) for i in instances], clones)
+    table = list(table)
+
+    def time_of(tab):
+        ctx.set_schedule(tab)
+        ctx.step(1)  # the rebuilt lists and the graph of this table
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(ctx.stream)
+        ctx.step(steps)
+        b.record(ctx.stream)
+        b.synchronize()
+        return a.elapsed_time(b) / steps
+
+    try:
+        ctx.set_schedule(table)
+        ctx.step(warmup)
+        order = sorted(buckets, key=lambda b: -sum(instances[k].n_particles for k in buckets[b]))
+        for b in order:
+            for path in candidates([instances[k] for k in buckets[b]]):
+                if path == table[b]:
+                    continue
+                trial = list(table)
+                trial[b] = path
+                t_cur, t_new = time_of(table), time_of(trial)
+                if log:
+                    log(f"mix: bucket 2^{b} {['default', 'group', 'wave', 'tiled'][table[b]]} {t_cur:.3f} ms, "
+                        f"{['default', 'group', 'wave', 'tiled'][path]} {t_new:.3f} ms")
+                if t_new < (1.0 - margin) * t_cur:
+                    table = trial
+        ctx.sync()
+    finally:
+        ctx.close()
+    return table

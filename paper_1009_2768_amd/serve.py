@@ -104,21 +104,46 @@ class Server:
         self.peak_active = 0
         self.ticks = 0
 
-    def tune(self, requests, per_bucket: int = 2, log=None):
-        """Choose the kernel path per cell-size bucket with the autotuner, timed on
-        copies of up to per_bucket requests of each bucket (before serving)."""
+    def tune(self, requests, per_bucket: int | None = None, max_particles: int = 8_000_000, refine: bool = True,
+             mix_particles: int | None = 100_000_000, log=None):
+        """Choose the kernel path per cell-size bucket with the autotuner (before
+        serving), timed on copies of the requests of each bucket, up to
+        max_particles particles (and per_bucket requests, if given) per bucket.
+        The sample is sized for throughput: with only a few requests a bucket
+        is timed by its latency alone, where the workgroup per cell wins, while
+        a served mix runs many of them at once, where a bucket of many small
+        cells runs faster one wave per cell.  refine: then refine the table on
+        the requests as one mix (autotune.refine_for_mix; up to mix_particles
+        particles, in arrival order), where the buckets share the GPU."""
         from . import size_bucket
         from .autotune import autotune
-        picked, count = [], {}
+        picked, count, total = [], {}, {}
         for r in requests:
             inst = instance_of(r, self.precision)
             b = size_bucket(inst)
-            if count.get(b, 0) < per_bucket:
-                count[b] = count.get(b, 0) + 1
-                picked.append((inst, r))
+            if per_bucket is not None and count.get(b, 0) >= per_bucket:
+                continue
+            if count.get(b, 0) and total[b] + inst.n_particles > max_particles:
+                continue
+            count[b] = count.get(b, 0) + 1
+            total[b] = total.get(b, 0) + inst.n_particles
+            picked.append((inst, r))
         insts = [i for i, _ in picked]
         parts = [self.initial(r, dtype=self.dtype) for _, r in picked]
-        table, timings = autotune(insts, parts, warmup=1, steps=2, log=log)
+        table, timings = autotune(insts, parts, warmup=1, steps=2, max_particles=max_particles, log=log)
+        if refine:
+            from .autotune import refine_for_mix
+            mix = [(instance_of(r, self.precision), r) for r in requests]
+            if mix_particles is not None:
+                kept, tot = [], 0
+                for inst, r in mix:
+                    if tot + inst.n_particles <= mix_particles:
+                        kept.append((inst, r))
+                        tot += inst.n_particles
+                mix = kept
+            del parts
+            table = refine_for_mix([i for i, _ in mix], [self.initial(r, dtype=self.dtype) for _, r in mix], table,
+                                   log=log)
         self.ctx.set_schedule(table)
         self.schedule = table
         return table, timings
