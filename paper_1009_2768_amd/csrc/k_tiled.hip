@@ -19,6 +19,16 @@
 // Partial sums are combined in tile order, so the result does not depend on
 // scheduling.  Same arithmetic as the whole-cell kernel; only the order of the
 // FP64 reductions differs (fixed per cell by its size).
+//
+// A cell whose previous step thermalized every particle (small eps) most
+// likely does so again: k_tile_prep then makes no roles and k_tile_bsum no
+// role-order block sums (only the VHS bound, in slot order).  An attempt that
+// thermalizes every particle needs neither: its sums are the whole cell's,
+// from k_tile_prep's tile sums (taken for every cell, predicted or not), and
+// every slot is thermalized.  When k_big_split finds that the first attempt
+// keeps or collides particles after all, k_tile_roles and k_tile_bfix make
+// the roles and the block sums; when a redo inside k_big_collide does,
+// k_big_collide makes them itself, in the same order.
 #include <hip/hip_runtime.h>
 
 #include "collide_core.h"
@@ -31,8 +41,61 @@ constexpr int kTT = 512;  // threads of every tiled kernel
 struct BigState {
     CellShared sh;
     unsigned long long ncoll;
-    uint32_t pad[2];
+    uint32_t roles;  // ROLES_MADE, ROLES_NONE (predicted, not needed so far), ROLES_FIX (made by the fix kernels)
+    uint32_t pad;
 };
+constexpr uint32_t ROLES_MADE = 0, ROLES_NONE = 1, ROLES_FIX = 2;
+
+#ifndef TRMC_TILE_LAZY_ROLES
+#define TRMC_TILE_LAZY_ROLES 1
+#endif
+constexpr bool kTileLazyRoles = TRMC_TILE_LAZY_ROLES != 0;
+
+// The cell's record of its previous step says every particle was thermalized.
+// Read only by the kernels before k_big_collide, which writes this step's record.
+__device__ __forceinline__ bool predicted_whole(const InstDev* I, uint32_t n)
+{
+    if constexpr (!kTileLazyRoles) return false;
+    const CellStats* st = I->stats;
+    return st->n == n && st->N0 == 0u && st->n_th == n && st->status == 0u;
+}
+
+// Roles of the slots [s_begin, s_end) (keyed permutation) and the slot of each.
+__device__ __forceinline__ void tile_roles(const Key& key, uint32_t n, gptr<uint32_t> role, gptr<uint32_t> fwd,
+                                           uint32_t s_begin, uint32_t s_end, uint32_t tid, uint32_t stride)
+{
+    const uint4 pk = draw(key, 0, TAG_PERM, 0);
+    const uint32_t pbits = perm_bits(n);
+    for (uint32_t i = s_begin + tid; i < s_end; i += stride) {
+        const uint32_t r = perm_inverse(i, n, pbits, pk);
+        role[i] = r;
+        fwd[r] = i;
+    }
+}
+
+// |v - m|^2, the same bits wherever it is taken (slot or role order).
+template <typename T>
+__device__ __forceinline__ double dist2(T x, T y, T z, double mx, double my, double mz)
+{
+#pragma clang fp contract(off)
+    const double dx = (double)x - mx, dy = (double)y - my, dz = (double)z - mz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// One role's terms of a block sum: v - m (3), (vx - m)^2, |v - m|^2 (returned too).
+template <typename T>
+__device__ __forceinline__ double bsum_terms(T x, T y, T z, double mx, double my, double mz, double (&sv)[5])
+{
+#pragma clang fp contract(off)
+    const double dx = (double)x - mx, dy = (double)y - my, dz = (double)z - mz;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    sv[0] += dx;
+    sv[1] += dy;
+    sv[2] += dz;
+    sv[3] += dx * dx;
+    sv[4] += d2;
+    return d2;
+}
 
 static_assert(sizeof(BigState) <= kBigStateBytes, "BigState exceeds its reserved bytes");
 
@@ -86,9 +149,11 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
     M.init(V.I, 0, 0, n);
     const gptr<uint32_t> role = M.role;
     const gptr<uint32_t> fwd = M.fwd;
-    const double c0 = (double)V.vx[0];
+    const bool make = !predicted_whole(V.I, n);
+    // sums of v_x - c0, v_y, v_z, (v_x - c0)^2, (v_y - c1)^2, (v_z - c2)^2 (c: the first particle)
+    const double c0 = (double)V.vx[0], c1 = (double)V.vy[0], c2 = (double)V.vz[0];
     constexpr int U = 4;
-    double s[4] = {0, 0, 0, 0};
+    double s[6] = {0, 0, 0, 0, 0, 0};
     T ax[U], ay[U], az[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -117,9 +182,14 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
                 s[1] += (double)ay[u];
                 s[2] += (double)az[u];
                 s[3] += dx * dx;
-                const uint32_t r = perm_inverse(i, n, pbits, pk);
-                role[i] = r;
-                fwd[r] = i;
+                const double dy = (double)ay[u] - c1, dz = (double)az[u] - c2;
+                s[4] += dy * dy;
+                s[5] += dz * dz;
+                if (make) {
+                    const uint32_t r = perm_inverse(i, n, pbits, pk);
+                    role[i] = r;
+                    fwd[r] = i;
+                }
             }
         }
 #pragma unroll
@@ -129,14 +199,32 @@ __global__ __launch_bounds__(kTT) void k_tile_prep(const CellRef* __restrict__ b
             az[u] = bz[u];
         }
     }
-    gsum<kTT, 4>(s, t_red);
+    gsum<kTT, 6>(s, t_red);
     if (threadIdx.x == 0) {
-        double* tp = V.I->tpart + 8ull * k;
+        double* tp = V.I->tpart + 8ull * k;  // [4] is the VHS bound (k_tile_bsum)
         tp[0] = s[0];
         tp[1] = s[1];
         tp[2] = s[2];
         tp[3] = s[3];
+        tp[5] = s[4];
+        tp[6] = s[5];
     }
+}
+
+// Roles of a cell found, after its split, to need them after all (ROLES_FIX).
+template <typename T>
+__global__ __launch_bounds__(kTT) void k_tile_roles(const CellRef* __restrict__ bigs,
+                                                    const uint32_t* __restrict__ prefix, uint32_t nb)
+{
+    uint32_t b, k;
+    tile_of(prefix, nb, blockIdx.x, b, k);
+    InstDev* I = bigs[b].inst;
+    if (big_state(I)->roles != ROLES_FIX) return;
+    const uint32_t n = I->cell_off[1] - I->cell_off[0];
+    const uint32_t s_begin = k * kTile, s_end = (s_begin + kTile < n) ? s_begin + kTile : n;
+    CellMem<T> M;
+    M.init(I, 0, 0, n);
+    tile_roles(Key{I->seed, I->uid, 0u, I->step}, n, M.role, M.fwd, s_begin, s_end, threadIdx.x, kTT);
 }
 
 // Cell mean from the prep partials (tile order; identical wherever computed).
@@ -165,8 +253,10 @@ __device__ __forceinline__ void cell_mean(const InstDev* I, uint32_t n, double c
 // cell mean (sum of v - m, of (vx - m)^2, of |v - m|^2), and for VHS the tile's
 // max |v - m|^2.  Any role range's sums are then a few block sums plus two
 // partial blocks (range_sums), so the attempts of the adaptive test cost
-// O(n / kRoleBlock) instead of a pass over the cell.
-template <typename T>
+// O(n / kRoleBlock) instead of a pass over the cell.  A cell predicted wholly
+// thermalized takes no block sums here (VHS: the max from its slots instead).
+// FIX: only the block sums, of a cell whose roles were made by k_tile_roles.
+template <typename T, bool FIX>
 __global__ __launch_bounds__(kTT) void k_tile_bsum(const CellRef* __restrict__ bigs, const uint32_t* __restrict__ prefix,
                                                    uint32_t nb)
 {
@@ -174,6 +264,9 @@ __global__ __launch_bounds__(kTT) void k_tile_bsum(const CellRef* __restrict__ b
     __shared__ double mean[3];
     uint32_t b, k;
     tile_of(prefix, nb, blockIdx.x, b, k);
+    if constexpr (FIX) {
+        if (big_state(bigs[b].inst)->roles != ROLES_FIX) return;
+    }
     CellView<T> V(bigs[b].inst);
     const uint32_t n = V.n;
     if (threadIdx.x == 0) {
@@ -187,27 +280,29 @@ __global__ __launch_bounds__(kTT) void k_tile_bsum(const CellRef* __restrict__ b
     const gptr<const uint32_t> fwd = M.fwd;
     const uint32_t r_begin = k * kTile, r_end = (r_begin + kTile < n) ? r_begin + kTile : n;
     double d2max = 0.0;
-    for (uint32_t b0 = r_begin; b0 < r_end; b0 += kRoleBlock) {
-        const uint32_t b1 = (b0 + kRoleBlock < r_end) ? b0 + kRoleBlock : r_end;
-        double sv[5] = {0, 0, 0, 0, 0};
-        for (uint32_t i = b0 + threadIdx.x; i < b1; i += kTT) {
-            const uint32_t sl = fwd[i];
-            const double dx = (double)V.vx[sl] - mx, dy = (double)V.vy[sl] - my, dz = (double)V.vz[sl] - mz;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            sv[0] += dx;
-            sv[1] += dy;
-            sv[2] += dz;
-            sv[3] += dx * dx;
-            sv[4] += d2;
+    if (FIX || !predicted_whole(V.I, n)) {
+        for (uint32_t b0 = r_begin; b0 < r_end; b0 += kRoleBlock) {
+            const uint32_t b1 = (b0 + kRoleBlock < r_end) ? b0 + kRoleBlock : r_end;
+            double sv[5] = {0, 0, 0, 0, 0};
+            for (uint32_t i = b0 + threadIdx.x; i < b1; i += kTT) {
+                const uint32_t sl = fwd[i];
+                const double d2 = bsum_terms<T>(V.vx[sl], V.vy[sl], V.vz[sl], mx, my, mz, sv);
+                d2max = d2 > d2max ? d2 : d2max;
+            }
+            gsum<kTT, 5>(sv, t_red);
+            if (threadIdx.x == 0) {
+                double* p = V.I->bsum + 8ull * (b0 / kRoleBlock);
+                for (int q = 0; q < 5; ++q) p[q] = sv[q];
+            }
+        }
+    } else if (!FIX && V.I->alpha != 0.0) {
+        // no block sums: the bound from the slots of the tile, in slot order
+        for (uint32_t i = r_begin + threadIdx.x; i < r_end; i += kTT) {
+            const double d2 = dist2<T>(V.vx[i], V.vy[i], V.vz[i], mx, my, mz);
             d2max = d2 > d2max ? d2 : d2max;
         }
-        gsum<kTT, 5>(sv, t_red);
-        if (threadIdx.x == 0) {
-            double* p = V.I->bsum + 8ull * (b0 / kRoleBlock);
-            for (int q = 0; q < 5; ++q) p[q] = sv[q];
-        }
     }
-    if (V.I->alpha != 0.0) {
+    if (!FIX && V.I->alpha != 0.0) {
         d2max = gmax<kTT>(d2max, t_red);
         if (threadIdx.x == 0) V.I->tpart[8ull * k + 4] = d2max;
     }
@@ -259,16 +354,38 @@ __global__ __launch_bounds__(kTT) void k_big_split(const CellRef* __restrict__ b
     CellShared& sh = shs[wave];
     const Key key{I->seed, I->uid, 0u, I->step};
     Levels L = levels_at(lds_levels + (size_t)wave * 5u * lv_stride, lv_stride);
+    bool pred = false;
     if (lane == 0) {
+        pred = predicted_whole(I, n);  // before this step's record is written
         const T* vx = reinterpret_cast<const T*>(I->vx[0]);
-        cell_mean(I, n, (double)vx[0], sh.mean[0], sh.mean[1], sh.mean[2], sh.Sn);
+        const T* vy = reinterpret_cast<const T*>(I->vy[0]);
+        const T* vz = reinterpret_cast<const T*>(I->vz[0]);
+        const double c0 = (double)vx[0], c1 = (double)vy[0], c2 = (double)vz[0];
+        cell_mean(I, n, c0, sh.mean[0], sh.mean[1], sh.mean[2], sh.Sn);
         double dmax = 0.0;
-        if (I->alpha != 0.0) {
-            const uint32_t nt = (n + kTile - 1) / kTile;
+        const uint32_t nt = (n + kTile - 1) / kTile;
+        if (I->alpha != 0.0)
             for (uint32_t t = 0; t < nt; ++t) dmax = fmax(dmax, I->tpart[8ull * t + 4]);
-        }
         cell_params(I, 0, n, dmax, sh);
         sh.overflow = n < 2 ? 1u : 0u;  // cells of fewer than 2 particles are skipped
+        // the whole cell's sums about its mean (tile order), for an attempt that
+        // thermalizes every particle: sum of v - m (rounding only) and of |v - m|^2
+        double a = 0, bb = 0, c = 0, d = 0, e = 0, f = 0;
+        for (uint32_t t = 0; t < nt; ++t) {
+            const double* tp = I->tpart + 8ull * t;
+            a += tp[0];
+            bb += tp[1];
+            c += tp[2];
+            d += tp[3];
+            e += tp[5];
+            f += tp[6];
+        }
+        const double nd = (double)n, dxm = a * (1.0 / nd);
+        const double ey = sh.mean[1] - c1, ez = sh.mean[2] - c2;
+        sh.all_th[0] = a - nd * dxm;
+        sh.all_th[1] = bb - nd * sh.mean[1];
+        sh.all_th[2] = c - nd * sh.mean[2];
+        sh.all_th[3] = (d - nd * dxm * dxm) + (e - nd * ey * ey) + (f - nd * ez * ez);
     }
     gsync<64>();
     if (n >= 2) split_levels<64>(key, n, sh.q, L, sh, lane, adaptive_look(I));
@@ -285,6 +402,9 @@ __global__ __launch_bounds__(kTT) void k_big_split(const CellRef* __restrict__ b
     if (lane == 0) {
         S->sh = sh;
         S->ncoll = 0;
+        // roles of a cell predicted wholly thermalized: none yet, or made now by the
+        // fix kernels when this attempt keeps or collides particles after all
+        S->roles = (!pred || n < 2) ? ROLES_MADE : (sh.split_rem == n ? ROLES_NONE : ROLES_FIX);
         if (n >= 2) {
             const uint32_t heavy = est > (double)kHeavyColl ? 1u : 0u;
             const uint32_t idx = atomicAdd(&cl.count[heavy], 1u);
@@ -399,6 +519,63 @@ __global__ __launch_bounds__(kTT) void k_big_level1(const CellRef* __restrict__ 
     }
 }
 
+// Roles and block sums of a cell, made by its group in k_big_collide when a
+// redo keeps or collides particles of a cell predicted wholly thermalized: the
+// same roles as k_tile_prep's, the same block sums bit for bit as
+// k_tile_bsum's (one role per thread of a 512-thread workgroup, each wave's
+// butterfly sum, then the waves in order; a one-wave group takes the waves in
+// turn).
+template <typename T, int G>
+__device__ void group_roles_bsums(InstDev* I, const Key& key, uint32_t n, const CellMem<T>& M, gptr<const T> vx,
+                                  gptr<const T> vy, gptr<const T> vz, double mx, double my, double mz, uint32_t tid,
+                                  double* red)
+{
+    tile_roles(key, n, M.role, M.fwd, 0u, n, tid, G);
+    gsync<G>();  // roles and slots visible to the group
+    const gptr<const uint32_t> fwd = M.fwd;
+    const uint32_t nblk = (n + kRoleBlock - 1u) / kRoleBlock;
+    for (uint32_t blk = 0; blk < nblk; ++blk) {
+        const uint32_t b0 = blk * kRoleBlock, b1 = (b0 + kRoleBlock < n) ? b0 + kRoleBlock : n;
+        double tot[5];
+        if constexpr (G == kTT) {
+            double sv[5] = {0, 0, 0, 0, 0};
+            const uint32_t i = b0 + tid;
+            if (i < b1) {
+                const uint32_t sl = fwd[i];
+                bsum_terms<T>(vx[sl], vy[sl], vz[sl], mx, my, mz, sv);
+            }
+            gsum<kTT, 5>(sv, red);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) tot[q] = sv[q];
+        } else {
+            static_assert(G == 64, "a group is one wave or the whole workgroup");
+#pragma unroll
+            for (int q = 0; q < 5; ++q) tot[q] = 0.0;
+            for (uint32_t w = 0; w < (uint32_t)(kTT / 64); ++w) {
+                double sv[5] = {0, 0, 0, 0, 0};
+                const uint32_t i = b0 + w * 64u + tid;
+                if (i < b1) {
+                    const uint32_t sl = fwd[i];
+                    bsum_terms<T>(vx[sl], vy[sl], vz[sl], mx, my, mz, sv);
+                }
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    double a = sv[q];
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+                    tot[q] += __shfl(a, 0);
+                }
+            }
+        }
+        if (tid == 0) {
+            double* p = I->bsum + 8ull * blk;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) p[q] = tot[q];
+        }
+    }
+    gsync<G>();  // block sums visible
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__ bigs, uint32_t lv_stride,
                                                      CellLists cl)
@@ -442,12 +619,25 @@ __global__ __launch_bounds__(kTT) void k_big_collide(const CellRef* __restrict__
     const T gT = (T)sh.g;
     unsigned long long ncoll = S->ncoll;
     bool first = true;  // the first attempt's level 1 was made by k_big_level1
+    bool roles_made = S->roles != ROLES_NONE;
     for (;;) {
         // sums of the unchanged and thermalized sets of this attempt
         const uint32_t N0 = sh.N0, R0 = sh.R0, P = n - N0;
         const uint32_t kept_end = N0 - sh.borrowed, leaf_end = N0 + (R0 < P ? R0 : P);
         double all[7];
-        attempt_sums<T, G>(vx, vy, vz, M.fwd, I->bsum, n, kept_end, leaf_end, mx, my, mz, tid, gl.red, all);
+        if (leaf_end == 0u) {
+            // every particle thermalized: the whole cell's sums (k_big_split)
+            all[0] = 0.0;
+            all[1] = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) all[2 + q] = sh.all_th[q];
+        } else {
+            if (!roles_made) {
+                group_roles_bsums<T, G>(I, key, n, M, vx, vy, vz, mx, my, mz, tid, gl.red);
+                roles_made = true;
+            }
+            attempt_sums<T, G>(vx, vy, vz, M.fwd, I->bsum, n, kept_end, leaf_end, mx, my, mz, tid, gl.red, all);
+        }
         uint32_t dummies = 0, viol = 0;
         double sfin = 0.0;
         // the majorant raised level by level (Remark 4.1), from the step's bound
@@ -519,7 +709,7 @@ __global__ __launch_bounds__(kTT) void k_tile_zsum(const CellRef* __restrict__ b
     M.init(I, 0, 0, n);
     double zs[4] = {0, 0, 0, 0};
     for (uint32_t s = s_begin + threadIdx.x; s < s_end; s += kTT) {
-        if (M.role[s] < leaf_end) continue;
+        if (leaf_end != 0u && M.role[s] < leaf_end) continue;  // (every slot thermalized: no roles read)
         const Vec3<T> z = Draws<T>::normals(key, s);  // keyed by the slot
         const double zx = (double)z.x, zy = (double)z.y, zz = (double)z.z;
         zs[0] += zx;
@@ -578,7 +768,7 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t i = s0 + u * kTT;
-            ro[u] = i < s_end ? M.role[i] : 0u;
+            ro[u] = (i < s_end && leaf_end != 0u) ? M.role[i] : 0u;  // (leaf_end 0: every slot thermalized)
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -603,7 +793,9 @@ __global__ __launch_bounds__(kTT) void k_tile_write(const CellRef* __restrict__ 
 
 #define TRMC_TILED_INSTANTIATE(T)                                                              \
     template __global__ void k_tile_prep<T>(const CellRef*, const uint32_t*, uint32_t, uint32_t*); \
-    template __global__ void k_tile_bsum<T>(const CellRef*, const uint32_t*, uint32_t);        \
+    template __global__ void k_tile_bsum<T, false>(const CellRef*, const uint32_t*, uint32_t); \
+    template __global__ void k_tile_bsum<T, true>(const CellRef*, const uint32_t*, uint32_t);  \
+    template __global__ void k_tile_roles<T>(const CellRef*, const uint32_t*, uint32_t);       \
     template __global__ void k_big_split<T>(const CellRef*, uint32_t, uint32_t, CellLists);    \
     template __global__ void k_big_tree<T, 64>(const CellRef*, uint32_t, CellLists);           \
     template __global__ void k_big_tree<T, kTT>(const CellRef*, uint32_t, CellLists);          \

@@ -37,8 +37,10 @@ struct CellLists {
 };
 template <typename T>
 __global__ void k_tile_prep(const CellRef*, const uint32_t*, uint32_t, uint32_t*);
-template <typename T>
+template <typename T, bool FIX>
 __global__ void k_tile_bsum(const CellRef*, const uint32_t*, uint32_t);
+template <typename T>
+__global__ void k_tile_roles(const CellRef*, const uint32_t*, uint32_t);
 template <typename T>
 __global__ void k_big_split(const CellRef*, uint32_t, uint32_t, CellLists);
 template <typename T, int G>
@@ -568,8 +570,12 @@ int launch_tiled(trmc_ctx* c, int k)
         const CellLists cl{c->cls_list[k], c->cls_count[k], c->max_cells};
         const uint32_t wblocks = (nt + 7) / 8;
         hipLaunchKernelGGL(k_tile_prep<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt, c->cls_count[k]);
-        hipLaunchKernelGGL(k_tile_bsum<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+        hipLaunchKernelGGL((k_tile_bsum<T, false>), dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
         hipLaunchKernelGGL(k_big_split<T>, dim3(wblocks), dim3(512), lds8, c->stream, bigs, nt, stride, cl);
+        // roles and block sums of the cells predicted wholly thermalized that are not
+        // (their blocks return at once for every other cell)
+        hipLaunchKernelGGL(k_tile_roles<T>, dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
+        hipLaunchKernelGGL((k_tile_bsum<T, true>), dim3(tiles), dim3(512), 0, c->stream, bigs, pre, nt);
         hipLaunchKernelGGL((k_big_tree<T, 64>), dim3(wblocks), dim3(512), lds8, c->stream, bigs, stride, cl);
         hipLaunchKernelGGL((k_big_tree<T, 512>), dim3(nt), dim3(512), lds1, c->stream, bigs, stride, cl);
         hipLaunchKernelGGL(k_big_level1<T>, dim3(nt * kLevel1Blocks), dim3(512), 0, c->stream, bigs, nt, stride);

@@ -159,6 +159,33 @@ def test_autotuner_table_is_valid(trmc):
     ctx.close()
 
 
+def test_mix_refinement_keeps_paths_valid(trmc):
+    """The refinement on the whole mix only picks, for a bucket, a path its cells
+    can take, steps copies only, and a table it returns runs the batch."""
+    T = trmc
+    from paper_1009_2768_amd.autotune import candidates, refine_for_mix
+    say("mix refinement")
+    insts, arrays = batch(T, T.FP32_MIXED)
+    parts = [T.device_particles(a["vx"], a["vy"], a["vz"], a.get("x"), i.precision) for i, a in zip(insts, arrays)]
+    before = [p["vx"].clone() for p in parts]
+    start = [T.PATH_GROUP] * T.SCHED_BUCKETS
+    table = refine_for_mix(insts, parts, start, warmup=1, steps=1)
+    assert len(table) == T.SCHED_BUCKETS
+    for b in range(T.SCHED_BUCKETS):
+        mine = [i for i in insts if T.size_bucket(i) == b]
+        if not mine:
+            assert table[b] == start[b]
+        else:
+            assert table[b] in candidates(mine), (b, table[b])
+    for p, b in zip(parts, before):
+        assert torch_equal(p["vx"], b)
+    ctx = T.Context(insts, parts)
+    ctx.set_schedule(table)
+    ctx.step(2)
+    ctx.sync()
+    ctx.close()
+
+
 def torch_equal(a, b):
     import torch
     return bool(torch.equal(a, b))

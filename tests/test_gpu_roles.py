@@ -6,8 +6,8 @@ cell sometimes wholly thermalized and sometimes not, and, for contrast, at ones
 where it keeps about half (sometimes more, sometimes less) or more than half of
 the particles (borrowed leaves, redos), every step's integers equal the FP64
 oracle's, the velocities stay within 1e-12 of it, and fused steps equal single
-steps bitwise; on the workgroup and the wave path, with fixed and adaptive
-depth."""
+steps bitwise; on the workgroup, the wave and the tile path, with fixed and
+adaptive depth."""
 import math
 import sys
 
@@ -38,7 +38,7 @@ def say(*a):
 # whole cell.  "kept": q n = n/2 - 1/2, so that half the steps keep half the
 # particles (N0 = n/2) and half do not (N0 = n/2 - 1).  "kept60": q = 0.6, every
 # step keeps more than half (adaptive: with borrowed leaves and redos).
-CASES = {"group": 2000, "wave": 300}
+CASES = {"group": 2000, "wave": 300, "tiled": 20000}
 FACTOR = {"fixed": 16.0, "adaptive": 100.0}
 
 
@@ -50,7 +50,7 @@ def eps_of(kind, trunc, n):
 
 
 @pytest.mark.parametrize("kind", ["thermal", "kept", "kept60"])
-@pytest.mark.parametrize("path", ["group", "wave"])
+@pytest.mark.parametrize("path", ["group", "wave", "tiled"])
 @pytest.mark.parametrize("trunc", ["fixed", "adaptive"])
 def test_roles_when_needed_match_oracle(trmc, orc, kind, path, trunc):
     T = trmc
@@ -61,7 +61,7 @@ def test_roles_when_needed_match_oracle(trmc, orc, kind, path, trunc):
     tr, otr = (T.FIXED, orc.FIXED) if trunc == "fixed" else (T.ADAPTIVE, orc.ADAPTIVE)
     mk = lambda: T.Instance(n_particles=n, eps=eps, alpha=0.0, trunc=tr, m_init=2, m_cap=64, uid=5, seed=11,
                             dt=0.05, precision=T.FP64, particle_weight=1.0 / n)
-    p = T.PATH_GROUP if path == "group" else T.PATH_WAVE
+    p = {"group": T.PATH_GROUP, "wave": T.PATH_WAVE, "tiled": T.PATH_TILED}[path]
     o = orc.Instance(*v, eps=eps, alpha=0.0, trunc=otr, m_init=2, m_cap=64, uid=5, seed=11, dt=0.05,
                      weight=1.0 / n)
     ctx = T.Context([mk()], [T.device_particles(*v, precision=T.FP64)])
@@ -95,8 +95,9 @@ def test_roles_when_needed_match_oracle(trmc, orc, kind, path, trunc):
         assert np.array_equal(fused[c], single[c]), c
 
 
+@pytest.mark.parametrize("sched", ["default", "tiled"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_restart_through_the_shortcuts_is_bitwise(trmc, prec):
+def test_restart_through_the_shortcuts_is_bitwise(trmc, prec, sched):
     """A run restarted from its saved state (step index, adaptive depths) equals
     the uninterrupted run bitwise, also where the step's shortcuts apply (roles
     made only when needed, the whole cell's sums from the moments pass, the
@@ -104,7 +105,7 @@ def test_restart_through_the_shortcuts_is_bitwise(trmc, prec):
     context takes from a blank record."""
     T = trmc
     P = T.FP64 if prec == "fp64" else T.FP32_MIXED
-    say("restart through the shortcuts", prec)
+    say("restart through the shortcuts", prec, sched)
     specs = [(3000, 1e-4, 0.0), (2000, 0.05 / math.log(100.0 * 2000), 0.0), (6000, 0.01, 1.0), (300, 1e-4, 1.0),
              (4000, 0.2, 1.0)]
     insts, arrs = [], []
@@ -115,8 +116,11 @@ def test_restart_through_the_shortcuts_is_bitwise(trmc, prec):
         arrs.append(v)
 
     def ctx_of(kw_list, arr_list):
-        return T.Context([T.Instance(**kw) for kw in kw_list],
-                         [T.device_particles(*a, precision=P) for a in arr_list])
+        ctx = T.Context([T.Instance(**kw) for kw in kw_list],
+                        [T.device_particles(*a, precision=P) for a in arr_list])
+        if sched == "tiled":
+            ctx.set_schedule([T.PATH_TILED] * T.SCHED_BUCKETS)
+        return ctx
 
     ctx = ctx_of(insts, arrs)
     ctx.step(8)
