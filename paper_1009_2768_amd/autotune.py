@@ -94,14 +94,16 @@ def autotune(instances, particles, warmup=1, steps=2, max_particles=8_000_000, m
     return table, timings
 
 
-def refine_for_mix(instances, particles, table, warmup=2, steps=2, margin=0.03, log=None):
+def refine_for_mix(instances, particles, table, warmup=2, steps=4, margin=0.03, log=None):
     """Coordinate descent of a schedule table on the whole mix: one context holds
     copies of every instance; bucket by bucket (largest share of particles first)
     each other path the bucket's cells can take replaces the current one when a
-    step of the whole mix is faster by more than `margin`.  Both tables of a
-    comparison are timed back to back on the same context (the schedule never
-    changes results, so the copies may be stepped under either).  Returns the
-    refined table."""
+    step of the whole mix is faster by more than `margin`.  The two tables of a
+    comparison are timed on the same context in the order current, trial, trial,
+    current, and each takes the mean of its two timings, so that a drift of the
+    step time over the comparison (the adaptive depths settling) favours neither
+    (the schedule never changes results, so the copies may be stepped under
+    either).  Returns the refined table."""
     import torch
     buckets: dict[int, list[int]] = {}
     for k, inst in enumerate(instances):
@@ -130,7 +132,9 @@ def refine_for_mix(instances, particles, table, warmup=2, steps=2, margin=0.03, 
                     continue
                 trial = list(table)
                 trial[b] = path
-                t_cur, t_new = time_of(table), time_of(trial)
+                a1, b1 = time_of(table), time_of(trial)
+                b2, a2 = time_of(trial), time_of(table)
+                t_cur, t_new = 0.5 * (a1 + a2), 0.5 * (b1 + b2)
                 if log:
                     log(f"mix: bucket 2^{b} {['default', 'group', 'wave', 'tiled'][table[b]]} {t_cur:.3f} ms, "
                         f"{['default', 'group', 'wave', 'tiled'][path]} {t_new:.3f} ms")
