@@ -94,11 +94,13 @@ def autotune(instances, particles, warmup=1, steps=2, max_particles=8_000_000, m
     return table, timings
 
 
-def refine_for_mix(instances, particles, table, warmup=2, steps=4, margin=0.03, log=None):
+def refine_for_mix(instances, particles, table, warmup=2, steps=4, margin=0.03, min_share=0.02, log=None):
     """Coordinate descent of a schedule table on the whole mix: one context holds
-    copies of every instance; bucket by bucket (largest share of particles first)
-    each other path the bucket's cells can take replaces the current one when a
-    step of the whole mix is faster by more than `margin`.  The two tables of a
+    copies of every instance; bucket by bucket (largest share of particles first,
+    buckets below min_share of the mix's particles left as they are: their paths
+    change a step of the whole mix by less than the timing noise) each other
+    path the bucket's cells can take replaces the current one when a step of the
+    whole mix is faster by more than `margin`.  The two tables of a
     comparison are timed on the same context in the order current, trial, trial,
     current, and each takes the mean of its two timings, so that a drift of the
     step time over the comparison (the adaptive depths settling) favours neither
@@ -125,7 +127,9 @@ def refine_for_mix(instances, particles, table, warmup=2, steps=4, margin=0.03, 
     try:
         ctx.set_schedule(table)
         ctx.step(warmup)
-        order = sorted(buckets, key=lambda b: -sum(instances[k].n_particles for k in buckets[b]))
+        share = {b: sum(instances[k].n_particles for k in buckets[b]) for b in buckets}
+        total = sum(share.values())
+        order = sorted((b for b in buckets if share[b] >= min_share * total), key=lambda b: -share[b])
         for b in order:
             for path in candidates([instances[k] for k in buckets[b]]):
                 if path == table[b]:
