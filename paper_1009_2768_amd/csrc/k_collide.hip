@@ -70,6 +70,12 @@ __device__ unsigned long long g_span[16384][2];
 #ifndef TRMC_SLOT_UNROLL
 #define TRMC_SLOT_UNROLL 2
 #endif
+#ifndef TRMC_SLOT_UNROLL_WAVE
+#define TRMC_SLOT_UNROLL_WAVE 4
+#endif
+#ifndef TRMC_WRITE_UNROLL_WAVE
+#define TRMC_WRITE_UNROLL_WAVE 8
+#endif
 #ifndef TRMC_WRITE_UNROLL
 #define TRMC_WRITE_UNROLL 4
 #endif
@@ -114,6 +120,8 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
 {
     constexpr int NGRP = NT / G;  // groups per workgroup
     static_assert(NGRP * sizeof(GroupLds<G>) <= kGroupLdsBytes, "group LDS exceeds the shared buffer");
+    // slots per thread per batch of the slot passes: a one-wave group keeps more loads in flight
+    constexpr int kU = G == 64 ? TRMC_SLOT_UNROLL_WAVE : kUnroll;
     extern __shared__ uint32_t lds_levels[];
     GroupLds<G>* const glds = reinterpret_cast<GroupLds<G>*>(g_group_lds);
 
@@ -209,20 +217,20 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
             bc2 = soff > 0 ? sh.mean[2] : st->mean[2];
         }
         // loads of the next batch are issued before the current batch is summed
-        T ax[kUnroll], ay[kUnroll], az[kUnroll];
+        T ax[kU], ay[kU], az[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const uint32_t i = tid + u * G;
             const bool ok = i < n;
             ax[u] = ok ? vx[i] : T(0);
             ay[u] = ok ? vy[i] : T(0);
             az[u] = ok ? vz[i] : T(0);
         }
-        for (uint32_t s0 = tid; s0 < n; s0 += G * kUnroll) {
-            T bx[kUnroll], by[kUnroll], bz[kUnroll];
-            const uint32_t s1 = s0 + G * kUnroll;
+        for (uint32_t s0 = tid; s0 < n; s0 += G * kU) {
+            T bx[kU], by[kU], bz[kU];
+            const uint32_t s1 = s0 + G * kU;
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 const uint32_t i = s1 + u * G;
                 const bool ok = i < n;
                 bx[u] = ok ? vx[i] : T(0);
@@ -230,7 +238,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                 bz[u] = ok ? vz[i] : T(0);
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 const uint32_t i = s0 + u * G;
                 if (i < n) {
                     const double dx = (double)ax[u] - c0;
@@ -257,7 +265,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 ax[u] = bx[u];
                 ay[u] = by[u];
                 az[u] = bz[u];
@@ -295,27 +303,27 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
             // two batches of loads in flight: the next batch is issued before
             // the current one is reduced
             double d2max = 0.0;
-            T ax2[kUnroll], ay2[kUnroll], az2[kUnroll];
+            T ax2[kU], ay2[kU], az2[kU];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 const uint32_t i = tid + u * G;
                 const bool ok = i < n;
                 ax2[u] = ok ? vx[i] : T(0);
                 ay2[u] = ok ? vy[i] : T(0);
                 az2[u] = ok ? vz[i] : T(0);
             }
-            for (uint32_t s0 = tid; s0 < n; s0 += G * kUnroll) {
-                T bx[kUnroll], by[kUnroll], bz[kUnroll];
+            for (uint32_t s0 = tid; s0 < n; s0 += G * kU) {
+                T bx[kU], by[kU], bz[kU];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t i = s0 + G * kUnroll + u * G;
+                for (int u = 0; u < kU; ++u) {
+                    const uint32_t i = s0 + G * kU + u * G;
                     const bool ok = i < n;
                     bx[u] = ok ? vx[i] : T(0);
                     by[u] = ok ? vy[i] : T(0);
                     bz[u] = ok ? vz[i] : T(0);
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < kU; ++u) {
                     if (s0 + u * G < n) {
                         const double dx = (double)ax2[u] - mx, dy = (double)ay2[u] - my, dz = (double)az2[u] - mz;
                         const double d2 = dx * dx + dy * dy + dz * dz;
@@ -323,7 +331,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < kU; ++u) {
                     ax2[u] = bx[u];
                     ay2[u] = by[u];
                     az2[u] = bz[u];
@@ -561,27 +569,27 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         const bool zready = fast && leaf_end == 0u;
         double zs[4] = {0, 0, 0, 0};
         // the next batch's roles are loaded while this batch's normals are drawn
-        uint32_t rz[kUnroll];
+        uint32_t rz[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const uint32_t i = tid + u * G;
             rz[u] = (kPrefetchRoles && !zready && i < n) ? (roles_ready ? M.role[i] : leaf_end) : 0u;
         }
-        for (uint32_t s0 = tid; !zready && s0 < n; s0 += G * kUnroll) {
-            uint32_t ro[kUnroll];
+        for (uint32_t s0 = tid; !zready && s0 < n; s0 += G * kU) {
+            uint32_t ro[kU];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 const uint32_t i = s0 + u * G;
                 if constexpr (kPrefetchRoles) {
                     ro[u] = rz[u];
-                    const uint32_t j = i + G * kUnroll;
+                    const uint32_t j = i + G * kU;
                     rz[u] = j < n ? (roles_ready ? M.role[j] : leaf_end) : 0u;
                 } else {
                     ro[u] = i < n ? (roles_ready ? M.role[i] : leaf_end) : 0u;
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kU; ++u) {
                 const uint32_t s = s0 + u * G;
                 if (s < n && ro[u] >= leaf_end) {
                     const Vec3<T> z = Draws<T>::normals(key, s);  // keyed by the slot
@@ -616,7 +624,7 @@ __device__ __attribute__((noinline)) void collide_cells(const CellRef* __restric
         const double a = uni(sh.a_th);
         const double u0 = uni(sh.ur[0]), u1 = uni(sh.ur[1]), u2 = uni(sh.ur[2]);
         const double z0 = uni(sh.zbar[0]), z1 = uni(sh.zbar[1]), z2 = uni(sh.zbar[2]);
-        constexpr int kWU = TRMC_WRITE_UNROLL;
+        constexpr int kWU = G == 64 ? TRMC_WRITE_UNROLL_WAVE : TRMC_WRITE_UNROLL;
         // the roles of a batch, then the finals of its leaf slots (final r of
         // leaf r); thermalized slots draw their normals again
         // the next batch's roles are loaded while this batch is written
