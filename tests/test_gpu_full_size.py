@@ -14,6 +14,8 @@ benchmark times.
 * Sod tube, 200 cells and 10^5 particles (hard spheres, eps = 1e-2): 200 steps in
   FP64 against the oracle (positions relative to the domain length), and in FP32
   with exact mass and energy kept to 1e-6 at every step.
+* The tile path at the serving stream's large sizes, with cells predicted wholly
+  thermalized from their previous step, every step against the oracle.
 """
 import math
 import os
@@ -238,6 +240,38 @@ def test_largest_serving_request_on_the_tile_path_fp64(trmc, orc):
     o = oracle_of(orc, inst, {"vx": vx, "vy": vy, "vz": vz})
     o.run(2)
     compare(o, got, mom, 1)
+
+
+@pytest.mark.parametrize("n,eps,alpha,steps", [(1_000_000, 1e-4, 1.0, 3),
+                                                (262_144, 0.05 / math.log(2.0 * 262_144), 0.0, 10)])
+def test_tile_path_predicted_thermal_cells_every_step(trmc, orc, n, eps, alpha, steps):
+    """Large cells on the tile path whose previous step thermalized every
+    particle make no roles and no block sums: at eps 1e-4 every step after the
+    first is such a step (hard spheres: the VHS bound from the slots); at the
+    threshold eps (q n = 1/2) some steps keep or collide particles after a
+    wholly thermalized one, so the fix kernels or the in-kernel fallback make
+    them.  Every step's integers equal the FP64 oracle's, the velocities stay
+    within 1e-12 of it."""
+    T = trmc
+    vx, vy, vz = W.bkw(n, 0.6, 0, 77) if alpha == 0.0 else W.bimaxwellian(n, seed=5, stream=6)
+    inst = T.Instance(n_particles=n, eps=eps, alpha=alpha, trunc=T.ADAPTIVE, m_cap=64, uid=41, seed=5,
+                      dt=0.05, particle_weight=1.0 / n, precision=T.FP64)
+    say(f"tile path, predicted thermal cells: n={n} eps={eps:.3g} alpha={alpha}")
+    ctx = T.Context([inst], [T.device_particles(vx, vy, vz, None, T.FP64)])
+    ctx.set_schedule(table_of(T, ",".join(f"{b}:tiled" for b in range(8, 21))))
+    o = oracle_of(orc, inst, {"vx": vx, "vy": vy, "vz": vz})
+    pattern = ""
+    for s in range(steps):
+        ctx.step(1)
+        o.run(1)
+        got, mom = ctx.read(0), ctx.moments(0)
+        compare(o, got, mom, 1)
+        pattern += "W" if int(o.last[0].n_th) == n else "."
+    ctx.close()
+    say(f"steps that thermalized the whole cell: {pattern}")
+    assert "W" in pattern[:-1]
+    if eps > 1e-3:
+        assert "W." in pattern  # a prediction that fails
 
 
 def test_slab_with_the_most_cells(trmc, orc):
