@@ -138,3 +138,49 @@ def test_restart_through_the_shortcuts_is_bitwise(trmc, prec, sched):
     for k in range(len(insts)):
         for c in ("vx", "vy", "vz"):
             assert np.array_equal(full[k][c], out[k][c]), (k, c)
+
+
+def test_tile_path_restarted_before_every_step_is_bitwise(trmc, orc):
+    """On the tile path, a cell predicted wholly thermalized whose first attempt
+    is wholly thermalized but whose redo keeps or collides particles makes its
+    roles and block sums inside the collision kernel, in the order of the tile
+    kernels.  A run restarted before every step (a blank record: no prediction,
+    roles and block sums from the tile kernels) equals the uninterrupted run bit
+    for bit; the oracle's attempt log shows that the run has such steps."""
+    T = trmc
+    n, steps = 20000, 12
+    eps = 0.05 / math.log(100.0 * n)
+    v = W.bkw(n, 0.6, 0, 321)
+    kw = dict(n_particles=n, eps=eps, alpha=0.0, trunc=T.ADAPTIVE, m_init=2, m_cap=64, uid=5, seed=11, dt=0.05,
+              precision=T.FP64, particle_weight=1.0 / n)
+    say("tile path restarted before every step", n, f"{eps:.4g}")
+    o = orc.Instance(*v, eps=eps, alpha=0.0, trunc=orc.ADAPTIVE, m_init=2, m_cap=64, uid=5, seed=11, dt=0.05,
+                     weight=1.0 / n)
+    fallback, prev = 0, False
+    for s_ in range(steps):
+        with orc.AttemptLog() as log:
+            o.run(1)
+        first = log.records[0]["n_th"] == n
+        last = int(o.last[0].n_th) == n
+        fallback += int(prev and first and not last)
+        prev = last
+    say(f"steps with a redo after a wholly thermalized first attempt of a predicted cell: {fallback}")
+    assert fallback >= 1
+
+    tiled = [T.PATH_TILED] * T.SCHED_BUCKETS
+    ctx = T.Context([T.Instance(**kw)], [T.device_particles(*v, precision=T.FP64)])
+    ctx.set_schedule(tiled)
+    ctx.step(steps)
+    full = ctx.read(0)
+    ctx.close()
+    cur, m_state = v, None
+    for s_ in range(steps):
+        ctx = T.Context([T.Instance(**dict(kw, step0=s_, m_state0=m_state))],
+                        [T.device_particles(*cur, precision=T.FP64)])
+        ctx.set_schedule(tiled)
+        ctx.step(1)
+        r = ctx.read(0)
+        ctx.close()
+        cur, m_state = (r["vx"], r["vy"], r["vz"]), r["m_state"]
+    for k, c in enumerate(("vx", "vy", "vz")):
+        assert np.array_equal(full[c], cur[k]), c
