@@ -6,8 +6,9 @@ size, the depth and the mix, so the tuner measures: the instances are grouped by
 schedule bucket (floor(log2) of particles per cell), and for every bucket each
 path the bucket's cells can take is timed on copies of that bucket's instances
 (a fresh copy per candidate, so every candidate steps the same states).  The
-result is a table for Context.set_schedule.  Results do not depend on the
-schedule, so tuning never changes what a run computes, only how fast.
+result is a table for Context.set_schedule.  The schedule changes how fast a
+run is, and otherwise only the rounding order of the FP64 cell sums (the last
+bits; see trmc_set_schedule): a fixed table gives the same bits every run.
 
 A mix whose buckets run together (the served form) is refined afterwards on the
 whole mix (refine_for_mix): timed bucket by bucket, a bucket of a few large cells
@@ -104,8 +105,8 @@ def refine_for_mix(instances, particles, table, warmup=2, steps=4, margin=0.03, 
     comparison are timed on the same context in the order current, trial, trial,
     current, and each takes the mean of its two timings, so that a drift of the
     step time over the comparison (the adaptive depths settling) favours neither
-    (the schedule never changes results, so the copies may be stepped under
-    either).  Returns the refined table."""
+    (the copies are thrown away, so they may be stepped under either).  Returns
+    the refined table."""
     import torch
     buckets: dict[int, list[int]] = {}
     for k, inst in enumerate(instances):
