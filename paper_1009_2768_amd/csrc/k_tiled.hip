@@ -7,7 +7,10 @@
 //                  permutation and its inverse), partial sums for the mean
 //   k_tile_bsum    tiles: sums over blocks of roles; max |v - mean|^2 (VHS majorant)
 //   k_big_split    cells: moments, tau, split (Alg. 4.2); light / heavy lists
+//   k_tile_roles,  tiles: roles and block sums of the cells predicted wholly
+//   k_tile_bsum<T, true>  thermalized whose split keeps or collides particles
 //   k_big_tree     cells: collision trees (Alg. 4.3)
+//   k_big_level1   cells x 32 workgroups: level 1 of the first attempt
 //   k_big_collide  cells: sums of the unchanged / thermalized sets from block
 //                  sums, collisions level by level (leaves read through the
 //                  slot of each role), adaptive test (Sec. 4.3); a rejected
@@ -26,8 +29,8 @@
 // thermalizes every particle needs neither: its sums are the whole cell's,
 // from k_tile_prep's tile sums (taken for every cell, predicted or not), and
 // every slot is thermalized.  When k_big_split finds that the first attempt
-// keeps or collides particles after all, k_tile_roles and k_tile_bfix make
-// the roles and the block sums; when a redo inside k_big_collide does,
+// keeps or collides particles after all, k_tile_roles and k_tile_bsum<T, true>
+// make the roles and the block sums; when a redo inside k_big_collide does,
 // k_big_collide makes them itself, in the same order.
 #include <hip/hip_runtime.h>
 
