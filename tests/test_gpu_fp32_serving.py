@@ -4,7 +4,7 @@ FP32-mixed keeps velocities and collision arithmetic in float and the cell sums
 and the conservation rescale in double.  With Maxwell molecules and a fixed depth
 the integer schedule equals the FP64 oracle's (same draws, q does not depend on
 the velocities), so the FP32 trajectory is a rounding perturbation of the oracle's;
-otherwise FP32 is judged by conservation (<= 1e-6 relative) and by cell moments
+otherwise FP32 is checked by conservation (<= 1e-6 relative) and by cell moments
 within 3 sigma of an oracle ensemble.  Serving: each result is the same alone
 and in the mix (bitwise).
 """
