@@ -87,6 +87,29 @@ def test_fp32_conservation(trmc, alpha, eps):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,eps,alpha", [(1_000_000, 1e-4, 1.0), (262_144, 0.05 / math.log(2.0 * 262_144), 0.0)])
+def test_fp32_conservation_on_the_tile_path(trmc, n, eps, alpha):
+    """FP32 conservation at every step on the tile path at the serving stream's
+    large sizes, where cells predicted wholly thermalized take the whole cell's
+    sums from the tile sums (and, at the threshold eps, predictions fail)."""
+    say("fp32 conservation, tile path", n, eps, alpha)
+    inst, a = inst_arrays(trmc, n, eps, alpha, trmc.ADAPTIVE, trmc.FP32_MIXED, uid=43)
+    parts = [trmc.device_particles(a["vx"], a["vy"], a["vz"], None, inst.precision)]
+    ctx = trmc.Context([inst], parts)
+    ctx.set_schedule([trmc.PATH_TILED] * trmc.SCHED_BUCKETS)
+    prev = ctx.read(0)
+    for _ in range(6):
+        ctx.step(1)
+        cur = ctx.read(0)
+        v0 = np.stack([prev["vx"], prev["vy"], prev["vz"]], 1).astype(np.float64)
+        v1 = np.stack([cur["vx"], cur["vy"], cur["vz"]], 1).astype(np.float64)
+        dp = np.abs(v1.sum(0) - v0.sum(0)).max() / np.abs(v0).sum()
+        de = abs((v1**2).sum() - (v0**2).sum()) / (v0**2).sum()
+        assert dp <= 1e-6 and de <= 1e-6, (dp, de)
+        prev = cur
+    ctx.close()
+
+
 def test_fp32_moments_within_3_sigma_of_oracle_ensemble(trmc, orc):
     """Hard spheres, adaptive depth: per-moment ensemble means (24 replicas) of the
     FP32 path within 3 sigma of the FP64 oracle's."""
